@@ -1,0 +1,202 @@
+"""Independent definitional re-implementations used to pin the oracle.
+
+Pure Python, written straight from the paper's definitions: no conflict
+table, no incremental evaluation -- every quantity is recomputed from the
+definition each time it is needed.  Slow on purpose; used on tiny inputs.
+Shares no code with oracle/ or with the GPU library.
+"""
+
+from __future__ import annotations
+
+from fractions import Fraction
+
+M32 = 0xFFFFFFFF
+
+
+# --- Philox4x32-10 (Salmon et al., SC'11), third independent copy ---------------
+def philox4x32_10(ctr, key):
+    x = [c & M32 for c in ctr]
+    k0, k1 = key[0] & M32, key[1] & M32
+    for r in range(10):
+        if r:
+            k0 = (k0 + 0x9E3779B9) & M32
+            k1 = (k1 + 0xBB67AE85) & M32
+        p0 = 0xD2511F53 * x[0]
+        p1 = 0xCD9E8D57 * x[2]
+        x = [((p1 >> 32) ^ x[1] ^ k0) & M32, p1 & M32, ((p0 >> 32) ^ x[3] ^ k1) & M32, p0 & M32]
+    return x
+
+
+def fmix32(h):
+    h &= M32
+    h ^= h >> 16
+    h = (h * 0x85EBCA6B) & M32
+    h ^= h >> 13
+    h = (h * 0xC2B2AE35) & M32
+    h ^= h >> 16
+    return h
+
+
+def draw(seed, slot, gen, tag, idx):
+    return philox4x32_10([0, slot, ((gen << 8) | tag) & M32, idx], [seed & M32, seed >> 32])
+
+
+# --- Latin square graph (Section 2.1) -------------------------------------------
+def reduced_graph(grid):
+    """Vertices (row-major empty cells that can take a symbol) and D*(v)."""
+    n = len(grid)
+    verts, dom, impossible = [], [], 0
+    for i in range(n):
+        for j in range(n):
+            if grid[i][j]:
+                continue
+            used = {grid[i][t] for t in range(n)} | {grid[t][j] for t in range(n)}
+            d = [k for k in range(1, n + 1) if k not in used]
+            if d:
+                verts.append((i, j))
+                dom.append(d)
+            else:
+                impossible += 1
+    return verts, dom, impossible
+
+
+def adjacent(a, b):
+    return a != b and (a[0] == b[0] or a[1] == b[1])
+
+
+def f_of(S):
+    return sum(1 for s in S if s == 0)
+
+
+def c_of(S, verts):
+    """Number of conflicting edges (Eq. 3-4)."""
+    c = 0
+    for a in range(len(verts)):
+        for b in range(a + 1, len(verts)):
+            if S[a] and S[a] == S[b] and adjacent(verts[a], verts[b]):
+                c += 1
+    return c
+
+
+def conflicting(S, verts, v):
+    return S[v] != 0 and any(S[u] == S[v] and adjacent(verts[u], verts[v]) for u in range(len(verts)))
+
+
+def brute_force_optimum(grid):
+    """Maximum number of filled cells over all legal extensions (DFS with a bound)."""
+    n = len(grid)
+    verts, dom, _ = reduced_graph(grid)
+    pre = sum(1 for i in range(n) for j in range(n) if grid[i][j])
+    best = [0]
+    S = [0] * len(verts)
+
+    def rec(t, filled):
+        if filled + (len(verts) - t) <= best[0]:
+            return
+        if t == len(verts):
+            best[0] = max(best[0], filled)
+            return
+        for k in dom[t]:
+            if all(not (S[u] == k and adjacent(verts[u], verts[t])) for u in range(t)):
+                S[t] = k
+                rec(t + 1, filled + 1)
+                S[t] = 0
+        rec(t + 1, filled)
+
+    rec(0, 0)
+    return pre + best[0]
+
+
+# --- PLITS re-derived by brute force (Section 3.3, Alg. 3) ------------------------
+def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
+    """Every iteration's chosen move, re-derived by evaluating F(S') from scratch
+    for every neighbour S' of N(S) = N_0(S) u N_c(S).  Returns (rows, S_out)."""
+    verts, dom, _ = reduced_graph(grid)
+    n = len(grid)
+    nv = len(verts)
+    S = list(S_in)
+    rows = []
+    for phase, iters in ((1, depth1), (2, depth2)):
+        phi = Fraction(1, 2) if phase == 1 else Fraction(nv)
+        scale = 2 if phase == 1 else 1  # F is compared as scale * (f + phi c)
+
+        def F(X):
+            return int(scale * (f_of(X) + phi * c_of(X, verts)))
+
+        tag = 0x11 if phase == 1 else 0x12
+        Fbest = F(S)
+        Sbest = list(S)
+        tabu = {}
+        for it in range(iters):
+            elig = [v for v in range(nv) if S[v] == 0 or conflicting(S, verts, v)]
+            if not elig:
+                break
+            w = draw(seed, slot, gen, tag, it)
+            Fc = F(S)
+            best = None
+            for v in elig:
+                for k in [0] + dom[v]:
+                    if k == S[v]:
+                        continue
+                    S2 = list(S)
+                    S2[v] = k
+                    delta = F(S2) - Fc
+                    if not (it >= tabu.get((v, k), 0) or Fc + delta < Fbest):
+                        continue
+                    key = (delta, fmix32(w[1] ^ (v * (n + 1) + k)))
+                    if best is None or key < best[0]:
+                        best = (key, v, k, delta)
+            if best is None:
+                rows.append((phase, it, -1, -1, 0, Fc, 1))
+                continue
+            _, v, k, delta = best
+            old = S[v]
+            S[v] = k
+            mp = sum(1 for u in range(nv) if S[u] == 0 or conflicting(S, verts, u))
+            T = ((w[0] * 10) >> 32) + (6 * mp) // 10
+            tabu[(v, old)] = it + 1 + T
+            Fn = F(S)
+            rows.append((phase, it, v, k, delta, Fn, 0))
+            if Fn < Fbest:
+                Fbest = Fn
+                Sbest = list(S)
+        S = Sbest
+    # final legality guard (Section 3.7): uncolour the most conflicting vertex first
+    while True:
+        cnts = [sum(1 for u in range(nv) if S[v] and S[u] == S[v] and adjacent(verts[u], verts[v]))
+                for v in range(nv)]
+        m = max(cnts) if cnts else 0
+        if m == 0:
+            break
+        S[cnts.index(m)] = 0
+    return rows, S
+
+
+# --- Population update, Alg. 4, transcribed literally ------------------------------
+def alg4_literal(f_all, D_all, nv, p, gamma, seed, gen):
+    """Alg. 4 with its two fixes: a candidate leaves P^all once examined, and a
+    short population is completed with rejected candidates in examination order.
+    e(S) = f(S); ties in e are broken by the SELECT draw, then by index."""
+    m = 2 * p
+
+    def key(x):
+        return (f_all[x], draw(seed, 0, gen, 0x21, x >> 2)[x & 3], x)
+
+    P_all = list(range(m))
+    P_next, rejected = [], []
+    s_best = min(P_all, key=key)
+    P_next.append(s_best)
+    P_all.remove(s_best)
+    while len(P_next) < p and P_all:
+        s_best = min(P_all, key=key)
+        dist = min(D_all[s_best][a] for a in P_next)
+        if dist > Fraction(nv, gamma):
+            P_next.append(s_best)
+        else:
+            rejected.append(s_best)
+        P_all.remove(s_best)
+    for x in rejected:
+        if len(P_next) >= p:
+            break
+        P_next.append(x)
+    return P_next
