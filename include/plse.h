@@ -1,0 +1,215 @@
+/*
+ * plse.h -- C ABI of the MI355X (gfx950) solver for the partial Latin square
+ * extension problem, after Goudet & Hao, "A massively parallel evolutionary
+ * algorithm for the partial Latin square extension problem".
+ *
+ * Every call returns an int status (PLSE_OK = 0) and never throws.  There is
+ * no global state: everything lives in a handle.  The library never allocates
+ * device memory: the caller attaches a workspace (e.g. a torch uint8 tensor)
+ * and passes a HIP stream; all device work is enqueued on that stream.
+ *
+ * Threading: one call at a time per handle (PLSE_E_BUSY otherwise).
+ */
+#ifndef PLSE_H
+#define PLSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PLSE_OK = 0,
+    PLSE_E_ARG = 1,        /* null pointer or argument out of range             */
+    PLSE_E_GRID = 2,       /* grid is not a partial Latin square                */
+    PLSE_E_WORKSPACE = 3,  /* no workspace attached, or too small               */
+    PLSE_E_HIP = 4,        /* a HIP runtime call failed (see plse_strerror)     */
+    PLSE_E_BUSY = 5,       /* the handle is already running a call              */
+    PLSE_PENDING = 6,      /* server: request not finished yet                  */
+    PLSE_E_PARAM = 7,      /* unknown parameter key or value out of range       */
+    PLSE_E_CAPACITY = 8    /* server: request cannot ever fit the budget        */
+};
+
+typedef struct plse_instance *plse_handle;
+
+/* Number of per-generation counters reported by plse_last_stats and the
+ * per-individual counter rows of plse_stage_plits, in this order:
+ * iterations, moves, idle iterations, candidates examined, eligible vertices
+ * (summed over iterations), conflict-table entries updated, best-solution
+ * snapshots, vertices uncoloured by the final repair. */
+#define PLSE_NCOUNTERS 8
+#define PLSE_MAX_GENERATIONS 65536
+#define PLSE_MAX_POPULATION 32768
+#define PLSE_HIST 64
+
+typedef struct {
+    int32_t generations_run;      /* <= requested generations (UB stop)         */
+    int32_t best_f;               /* uncoloured vertices of S*                  */
+    int32_t best_generation;      /* generation in which S* was found           */
+    int32_t reserved;
+    uint64_t totals[PLSE_NCOUNTERS];
+} plse_stats;
+
+/*
+ * plse_create -- build the reduced Latin square graph of one instance.
+ *
+ * Section 2.1 (Latin square graph, list colouring with D(v)) and Alg. 1 of
+ * Section 2.2 (preprocessing): prefilled cells are removed and their symbols
+ * deleted from the domains of the empty cells in the same row and column; an
+ * empty cell left with no symbol is impossible and counted in l.  The upper
+ * bound is n^2 - l, or n^2 - 2 when l = 1 (Section 2.2).
+ *
+ * n:    order, 1..127.
+ * grid: host pointer, n*n int8 row-major; 0 = empty, 1..n = symbol.  Copied.
+ * out:  receives the handle (free with plse_destroy).
+ * Errors: PLSE_E_ARG (null, n out of range), PLSE_E_GRID (a value outside
+ * [0, n] or a symbol repeated in a row or column).
+ */
+int plse_create(int32_t n, const int8_t *grid, plse_handle *out);
+
+/* |V| of the reduced graph, l (impossible cells), upper bound on the score. */
+int plse_info(plse_handle h, int32_t *num_vertices, int32_t *num_impossible,
+              int32_t *upper_bound);
+
+/* Sizes of the reduced graph: order n, |V|, sum over v of |D*(v)| (entries of
+ * one conflict table) and the device row stride; any pointer may be NULL. */
+int plse_sizes(plse_handle h, int32_t *n, int32_t *num_vertices, int32_t *domain_entries,
+               int32_t *stride);
+
+/* Device row stride (bytes) of one individual: |V| rounded up to 16.
+ * Stage calls read and write populations as [count][stride] uint8. */
+int plse_row_stride(plse_handle h, int32_t *stride);
+
+/*
+ * plse_set_param / plse_get_param -- solver parameters (Table 1, Section 3.3).
+ *   "depth"       total tabu iterations per individual and generation; phase 2
+ *                 gets min(2|V|, depth), phase 1 the rest (default 10 n^2)
+ *   "depth1", "depth2"  phase lengths set directly (paper: 100|V| and 2|V|)
+ *   "alpha_num", "alpha_den"   tenure factor alpha (6/10)
+ *   "beta_num", "beta_den"     AUX beta (20/1, Eq. 9)
+ *   "spacing"     minimum spacing factor gamma of Section 3.4 (10)
+ *   "stop_at_ub"  1: stop after the generation whose best reaches the bound
+ *   "nn_history"  partner-history length, 0..64 (64)
+ *   "conf_bytes"  1 or 2: bytes per conflict-table entry (default 1; 2 is the
+ *                 int16 table)
+ *   "waves_per_block" 1, 2 or 4: PLITS launch shape (default: chosen from the
+ *                 LDS footprint)
+ * Errors: PLSE_E_PARAM.
+ */
+int plse_set_param(plse_handle h, const char *key, int64_t value);
+int plse_get_param(plse_handle h, const char *key, int64_t *value);
+
+/* Bytes of device workspace a solve with this population needs. */
+int plse_workspace_bytes(plse_handle h, int32_t population, size_t *bytes);
+
+/* Attach caller-owned device memory (256-byte aligned); it must outlive every
+ * solve and stage call.  Passing NULL detaches. */
+int plse_attach_workspace(plse_handle h, void *device_ptr, size_t bytes);
+
+/*
+ * plse_solve -- run the memetic algorithm (Alg. 2) on the attached workspace.
+ *
+ * Initial population (Section 3.2), then per generation: the two-phase tabu
+ * search PLITS on every offspring (Section 3.3, Alg. 3), best-solution
+ * saving, Hamming distances over both populations (Eq. 8), the population
+ * update (Alg. 4), nearest-neighbour parent matching (Section 3.5.1) and the
+ * AUX crossover (Alg. 5, Eq. 9).  Stops after `generations`, or earlier with
+ * stop_at_ub when the score reaches the upper bound.
+ *
+ * population: 2..32768.   generations: 1..65536.   seed: any 64-bit value.
+ * stream:     hipStream_t (may be NULL = default stream).
+ * best_grid:  host, n*n int8: the prefilled cells plus the best colouring S*;
+ *             impossible and uncoloured cells are 0.
+ * filled:     host, number of non-zero cells of best_grid (<= upper bound).
+ * The result depends only on (grid, parameters, population, generations,
+ * seed).  Returns after the results are on the host.
+ * Errors: PLSE_E_ARG, PLSE_E_WORKSPACE, PLSE_E_HIP, PLSE_E_BUSY.
+ */
+int plse_solve(plse_handle h, int32_t population, int32_t generations, uint64_t seed,
+               void *stream, int8_t *best_grid, int32_t *filled);
+
+/*
+ * Session form of plse_solve, for callers that drive generations themselves:
+ *   plse_begin  uploads the instance, builds the initial population and
+ *               prepares the generation graphs (enqueued on `stream`);
+ *   plse_step   enqueues `generations` more generations of Alg. 2 (no host
+ *               synchronisation); HIP events are recorded on `stream` before
+ *               and after each tabu-search launch and at the end of each
+ *               generation;
+ *   plse_end    waits for the stream, then returns the best grid as
+ *               plse_solve does and fills the statistics and timings.
+ * plse_solve(h, p, G, ...) is plse_begin + plse_step(G) + plse_end.
+ * A session holds the handle's workspace until plse_end.
+ * Errors: PLSE_E_ARG (no session, more than PLSE_MAX_GENERATIONS steps),
+ * PLSE_E_WORKSPACE, PLSE_E_HIP, PLSE_E_BUSY.
+ */
+int plse_begin(plse_handle h, int32_t population, uint64_t seed, void *stream);
+int plse_step(plse_handle h, int32_t generations, void *stream);
+int plse_end(plse_handle h, void *stream, int8_t *best_grid, int32_t *filled);
+
+/* Per-generation GPU times of the last session, from the HIP events of
+ * plse_step: plits_ms[g] spans the tabu-search launch of generation g,
+ * rest_ms[g] the best/distance/selection/matching/crossover kernels.  *steps
+ * receives the number of generations stepped; either array may be NULL. */
+int plse_last_timing(plse_handle h, int32_t *steps, float *plits_ms, float *rest_ms);
+
+/* Statistics of the last solve; per_gen_best_f (may be NULL) receives the
+ * best f after each generation (generations_run entries) and per_gen_counters
+ * (may be NULL) PLSE_NCOUNTERS u64 per generation. */
+int plse_last_stats(plse_handle h, plse_stats *out, int32_t *per_gen_best_f,
+                    uint64_t *per_gen_counters);
+
+void plse_destroy(plse_handle h);
+const char *plse_strerror(int status);
+
+/*
+ * Stage calls: one step of the path on caller device buffers, with the
+ * handle's attached workspace (sized for at least `population`) as scratch.
+ * They enqueue on `stream` and return without synchronising.  Populations are
+ * [count][stride] uint8 device arrays (stride from plse_row_stride).
+ */
+
+/* Randomised greedy legal colourings of slots 0..p-1 (Section 3.2).
+ * S: device [p][stride] out; f: device int32 [p] out (uncoloured counts). */
+int plse_stage_init(plse_handle h, int32_t population, uint64_t seed, void *stream,
+                    uint8_t *S, int32_t *f);
+
+/* PLITS (Section 3.3, Alg. 3) of generation `gen` on slots 0..p-1.
+ * S_in: device [p][stride]; S_out: device [p][stride] (distinct from S_in);
+ * f_out: device int32 [p]; counters: device uint64 [p][PLSE_NCOUNTERS]. */
+int plse_stage_plits(plse_handle h, int32_t population, int32_t gen, uint64_t seed,
+                     void *stream, const uint8_t *S_in, uint8_t *S_out, int32_t *f_out,
+                     uint64_t *counters);
+
+/* Hamming distances (Eq. 8) between all pairs of m individuals.
+ * S: device [m][stride]; D: device int16 [m][m] out.  m <= 2*population. */
+int plse_stage_distances(plse_handle h, int32_t m, void *stream, const uint8_t *S, int16_t *D);
+
+/* Population update (Alg. 4) over 2p candidates (P_t = 0..p-1, P' = p..2p-1).
+ * f_all: device int32 [2p]; D_all: device int16 [2p][2p];
+ * accepted: device int32 [p] out, the next population in slot order. */
+int plse_stage_select(plse_handle h, int32_t population, int32_t gen, uint64_t seed,
+                      void *stream, const int32_t *f_all, const int16_t *D_all,
+                      int32_t *accepted);
+
+/* Parent matching (Section 3.5.1) with partner history.
+ * D: device int16 [p][p]; uid: device uint64 [p]; hist: device uint64
+ * [p][PLSE_HIST] and hcount: device int32 [p], both updated in place;
+ * partner, dpart: device int32 [p] out. */
+int plse_stage_match(plse_handle h, int32_t population, void *stream, const int16_t *D,
+                     const uint64_t *uid, uint64_t *hist, int32_t *hcount, int32_t *partner,
+                     int32_t *dpart);
+
+/* AUX crossover (Alg. 5, Eq. 9) of generation `gen`.
+ * S: device [p][stride]; partner, dpart: device int32 [p];
+ * S_off: device [p][stride] out. */
+int plse_stage_aux(plse_handle h, int32_t population, int32_t gen, uint64_t seed, void *stream,
+                   const uint8_t *S, const int32_t *partner, const int32_t *dpart,
+                   uint8_t *S_off);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLSE_H */

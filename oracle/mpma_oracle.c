@@ -249,6 +249,16 @@ void orc_init(const void *h, uint64_t seed, int32_t p, uint8_t *S, int32_t *f) {
     }
 }
 
+void orc_init_slots(const void *h, uint64_t seed, int32_t ns, const int32_t *slots, uint8_t *S,
+                    int32_t *f) {
+    const inst_t *I = (const inst_t *)h;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < ns; i++) {
+        init_one(I, seed, (uint32_t)slots[i], S + (size_t)i * I->nv);
+        f[i] = count_uncoloured(S + (size_t)i * I->nv, I->nv);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* PLITS: two-phase tabu search (Section 3.3, Alg. 3).                       */
 /* ------------------------------------------------------------------------ */

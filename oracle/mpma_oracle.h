@@ -78,6 +78,9 @@ uint32_t orc_fmix32(uint32_t x);
 
 /* Randomised greedy legal initial colourings of slots 0..p-1. */
 void orc_init(const void *h, uint64_t seed, int32_t p, uint8_t *S, int32_t *f);
+/* The same for the listed slots only (row i of S is slot slots[i]). */
+void orc_init_slots(const void *h, uint64_t seed, int32_t ns, const int32_t *slots, uint8_t *S,
+                    int32_t *f);
 
 /* PLITS on `ns` individuals; slot ids key the random streams.
  * S_in/S_out: ns*|V| colours.  counters: ns*ORC_NCOUNTERS. */

@@ -55,6 +55,7 @@ def lib():
         L.orc_fmix32.restype = u32
         L.orc_fmix32.argtypes = [u32]
         L.orc_init.argtypes = [P, u64, i32, P, P]
+        L.orc_init_slots.argtypes = [P, u64, i32, P, P, P]
         L.orc_plits.argtypes = [P, P, u64, i32, i32, P, P, P, P, P]
         L.orc_plits_trace.restype = i32
         L.orc_plits_trace.argtypes = [P, P, u64, i32, i32, P, i32, P]
@@ -142,6 +143,13 @@ class Instance:
         S = np.zeros((p, self.nv), dtype=np.uint8)
         f = np.zeros(p, dtype=np.int32)
         lib().orc_init(self.h, seed, p, _ptr(S), _ptr(f))
+        return S, f
+
+    def init_slots(self, seed: int, slots):
+        slots = np.ascontiguousarray(np.asarray(slots, dtype=np.int32))
+        S = np.zeros((len(slots), self.nv), dtype=np.uint8)
+        f = np.zeros(len(slots), dtype=np.int32)
+        lib().orc_init_slots(self.h, seed, len(slots), _ptr(slots), _ptr(S), _ptr(f))
         return S, f
 
     def plits(self, params, seed: int, gen: int, slots, S_in):

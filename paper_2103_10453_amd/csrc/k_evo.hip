@@ -1,0 +1,606 @@
+// k_evo.hip -- the per-generation kernels around the tabu search on gfx950:
+// best-solution saving, Hamming distances (Eq. 8) as bit-sliced tiles, the
+// population update (Alg. 4), nearest-neighbour parent matching
+// (Section 3.5.1) and the AUX crossover (Alg. 5, Eq. 9), plus the small
+// control kernels of the generation graph.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace plse {
+
+// ---------------------------------------------------------------------------
+// control
+// ---------------------------------------------------------------------------
+__global__ void ctl_reset_kernel(Ctl *ctl) {
+    if (threadIdx.x == 0) {
+        ctl->gen = 0;
+        ctl->stop = 0;
+        ctl->fstar = INT32_MAX;
+        ctl->best_gen = 0;
+        ctl->gens_run = 0;
+    }
+}
+
+__global__ void gen_begin_kernel(Ctl *ctl) {
+    if (threadIdx.x == 0 && !ctl->stop) ctl->gen += 1;
+}
+
+// Fresh population bookkeeping: uid = slot, empty partner history, and the
+// first offspring population is the initial population itself (Alg. 2).
+__global__ void pop_setup_kernel(int32_t p, int32_t stride, uint64_t *uid, int32_t *hc,
+                                 const uint8_t *S, uint8_t *S_off) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (size_t)p) {
+        uid[i] = i;
+        hc[i] = 0;
+    }
+    const size_t nq = (size_t)p * (stride >> 4);
+    for (size_t q = i; q < nq; q += (size_t)gridDim.x * blockDim.x)
+        reinterpret_cast<uint4 *>(S_off)[q] = reinterpret_cast<const uint4 *>(S)[q];
+}
+
+// ---------------------------------------------------------------------------
+// best-solution saving (Alg. 2): argmin f over the improved offspring, ties to
+// the lowest slot; S* replaced only on strict improvement.  Also sums the
+// per-individual counters of the generation and sets the bound stop flag.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void best_kernel(const BestArgs a) {
+    if (a.ctl->stop) return;
+    const int g = a.ctl->gen;
+    __shared__ uint64_t kmin[16];
+    __shared__ uint64_t csum[16][kCounters];
+    __shared__ int improved;
+    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint64_t key = ~0ull;
+    uint64_t c[kCounters];
+#pragma unroll
+    for (int q = 0; q < kCounters; ++q) c[q] = 0;
+    for (int i = tid; i < a.p; i += blockDim.x) {
+        const uint64_t k = ((uint64_t)(uint32_t)a.f_new[i] << 32) | (uint32_t)i;
+        key = k < key ? k : key;
+#pragma unroll
+        for (int q = 0; q < kCounters; ++q) c[q] += a.cnt[(size_t)i * kCounters + q];
+    }
+    key = wave_min_u64(key);
+#pragma unroll
+    for (int q = 0; q < kCounters; ++q) c[q] = wave_sum_u64(c[q]);
+    if (lane == 0) {
+        kmin[wv] = key;
+#pragma unroll
+        for (int q = 0; q < kCounters; ++q) csum[wv][q] = c[q];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t k = ~0ull;
+        uint64_t s[kCounters] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            k = kmin[w] < k ? kmin[w] : k;
+            for (int q = 0; q < kCounters; ++q) s[q] += csum[w][q];
+        }
+        const int32_t fb = (int32_t)(k >> 32);
+        improved = 0;
+        if (fb < a.ctl->fstar) {
+            a.ctl->fstar = fb;
+            a.ctl->best_gen = g;
+            improved = 1 + (int)(uint32_t)k;  // slot + 1
+        }
+        GenStat &gs = a.stats[g - 1];
+        gs.best_f = a.ctl->fstar;
+        for (int q = 0; q < kCounters; ++q) gs.cnt[q] = s[q];
+        a.ctl->gens_run = g;
+        if (a.stop_at_ub && a.nsq_minus_l - a.ctl->fstar == a.ub) a.ctl->stop = 1;
+    }
+    __syncthreads();
+    if (improved) {
+        const uint8_t *src = a.S_new + (size_t)(improved - 1) * a.stride;
+        for (int q = tid; q < (a.stride >> 4); q += blockDim.x)
+            reinterpret_cast<uint4 *>(a.Sstar)[q] = reinterpret_cast<const uint4 *>(src)[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hamming distances (Eq. 8), bit-sliced.  pack: colour bit b of vertices
+// 32w..32w+31 of row x -> planes[(x*W + w)*B + b].  A pair differs at v iff
+// some plane differs, so D = sum_w popcount(OR_b (a_b XOR c_b)).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void pack_kernel(const PackArgs a) {
+    if (a.ctl && a.ctl->stop) return;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)a.m * a.W) return;
+    const int x = (int)(t / a.W), w = (int)(t % a.W);
+    const uint8_t *row = a.S + (size_t)x * a.stride;
+    uint32_t pl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int v0 = w * 32;
+    const int vend = min(a.nv, v0 + 32);
+    for (int v = v0; v < vend; ++v) {
+        const uint32_t s = row[v];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) pl[b] |= ((s >> b) & 1u) << (v - v0);
+    }
+    uint32_t *dst = a.planes + t * a.B;
+    for (int b = 0; b < a.B; ++b) dst[b] = pl[b];
+}
+
+constexpr int kTile = 64;   // rows and columns per distance tile
+constexpr int kCW = 8;      // words of 32 vertices staged per step
+
+
+// One 64x64 tile (I <= J) per 256-thread workgroup; each thread owns a 4x4
+// block of pairs (rows ty+16i, columns tx+16j).  Both D[I][J] and its mirror
+// are written through an LDS staging tile so that stores are row-contiguous.
+template <int B>
+__global__ __launch_bounds__(256) void dist_kernel(const DistArgs a) {
+    if (a.ctl && a.ctl->stop) return;
+    constexpr int PITCH = kCW * B + 1;  // odd pitch: rows fall in distinct banks
+    __shared__ uint32_t As[kTile * PITCH];
+    __shared__ uint32_t Bs[kTile * PITCH];
+    __shared__ int16_t Dt[kTile][kTile + 2];
+    // triangular tile index -> (I, J), I <= J
+    const long t = blockIdx.x;
+    long J = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    while (J * (J + 1) / 2 > t) --J;
+    const long I = t - J * (J + 1) / 2;
+    const int r0 = (int)I * kTile, c0 = (int)J * kTile;
+    const int tid = (int)threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    uint32_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0u;
+
+    for (int w0 = 0; w0 < a.W; w0 += kCW) {
+        const int nw = min(kCW, a.W - w0);
+        // stage kTile rows x nw words x B planes for both sides
+        for (int q = tid; q < kTile * kCW * B; q += 256) {
+            const int row = q / (kCW * B), rem = q % (kCW * B);
+            const int wc = rem / B;
+            uint32_t va = 0u, vb = 0u;
+            if (wc < nw) {
+                const int ra = r0 + row, rb = c0 + row;
+                if (ra < a.m) va = a.planes[((size_t)ra * a.W + w0) * B + rem];
+                if (rb < a.m) vb = a.planes[((size_t)rb * a.W + w0) * B + rem];
+            }
+            As[row * PITCH + rem] = va;
+            Bs[row * PITCH + rem] = vb;
+        }
+        __syncthreads();
+        for (int wc = 0; wc < nw; ++wc) {
+            uint32_t ra[4][B], rb[4][B];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    ra[i][b] = As[(ty + 16 * i) * PITCH + wc * B + b];
+                    rb[i][b] = Bs[(tx + 16 * i) * PITCH + wc * B + b];
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t x = 0u;
+#pragma unroll
+                    for (int b = 0; b < B; ++b) x |= ra[i][b] ^ rb[j][b];
+                    acc[i][j] += (uint32_t)__popc(x);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Dt[ty + 16 * i][tx + 16 * j] = (int16_t)acc[i][j];
+    __syncthreads();
+    // rows of the tile: D[r0 + row][c0 .. c0+63]
+    for (int q = tid; q < kTile * kTile; q += 256) {
+        const int row = q >> 6, col = q & 63;
+        const int gr = r0 + row, gc = c0 + col;
+        if (gr < a.m && gc < a.m) a.D[(size_t)gr * a.ld + gc] = Dt[row][col];
+    }
+    if (I != J) {
+        for (int q = tid; q < kTile * kTile; q += 256) {
+            const int row = q >> 6, col = q & 63;  // mirror: D[c0 + row][r0 + col]
+            const int gr = c0 + row, gc = r0 + col;
+            if (gr < a.m && gc < a.m) a.D[(size_t)gr * a.ld + gc] = Dt[col][row];
+        }
+    }
+}
+
+hipError_t launch_distances(const Ctl *ctl, const uint8_t *S, uint32_t *planes, int16_t *D,
+                            int m, int nv, int stride, int ld, int B, hipStream_t stream) {
+    const int W = (nv + 31) / 32;
+    PackArgs pa{ctl, S, planes, m, nv, stride, W, B};
+    const size_t nt = (size_t)m * W;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, pa);
+    const int nt1 = (m + kTile - 1) / kTile;
+    DistArgs da{ctl, planes, D, m, W, ld, nt1};
+    const unsigned ntri = (unsigned)((long)nt1 * (nt1 + 1) / 2);
+    switch (B) {
+#define PLSE_DIST_CASE(b) \
+    case b: hipLaunchKernelGGL(dist_kernel<b>, dim3(ntri), dim3(256), 0, stream, da); break;
+        PLSE_DIST_CASE(1)
+        PLSE_DIST_CASE(2)
+        PLSE_DIST_CASE(3)
+        PLSE_DIST_CASE(4)
+        PLSE_DIST_CASE(5)
+        PLSE_DIST_CASE(6)
+        PLSE_DIST_CASE(7)
+#undef PLSE_DIST_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Population update (Alg. 4)
+// ---------------------------------------------------------------------------
+// close lists: for candidate x, the candidates y != x with spacing*D(x,y) <= |V|
+// (those x excludes once accepted); deg[x] counts them, adj keeps the first kAdj.
+
+__global__ __launch_bounds__(256) void close_kernel(const CloseArgs a) {
+    if (a.ctl && a.ctl->stop) return;
+    const int x = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (x >= a.m) return;
+    const int lane = lane_id();
+    const int16_t *row = a.D + (size_t)x * a.ld;
+    uint32_t cnt = 0;
+    for (int y0 = 0; y0 < a.m; y0 += 64) {
+        const int y = y0 + lane;
+        const bool cl = (y < a.m) && (y != x) && (a.spacing * (int64_t)row[y] <= (int64_t)a.nv);
+        const uint64_t msk = ballot(cl);
+        const uint32_t pos = cnt + rank_below(msk);
+        if (cl && pos < (uint32_t)kAdj) a.adj[(size_t)x * kAdj + pos] = (uint16_t)y;
+        cnt += (uint32_t)__popcll(msk);
+    }
+    if (lane == 0) a.deg[x] = (int32_t)cnt;
+}
+
+
+// One workgroup: keys (f, SELECT draw, index) sorted by a bitonic network,
+// then wave 0 scans them in order.  A candidate is accepted iff the population
+// is not full and no accepted candidate is close to it; the blocked set (the
+// union of the close lists of accepted candidates) lives in an LDS bitmap.
+// Lanes take 64 candidates at a time: the candidates up to the first
+// unblocked one with a non-empty close list are decided together.
+__global__ __launch_bounds__(1024) void select_kernel(const SelectArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    int gen = a.gen_fixed;
+    if (gen == 0) {
+        if (a.ctl->stop) return;
+        gen = a.ctl->gen;
+    }
+    const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+    const int m = a.m, P2 = a.pow2;
+    uint32_t *blocked = reinterpret_cast<uint32_t *>(lds);          // [(m+31)/32]
+    const int nbw = (m + 31) / 32;
+    uint64_t *K = a.keys_in_lds ? reinterpret_cast<uint64_t *>(lds + ((nbw * 4 + 15) & ~15))
+                                : a.keys_g;
+    for (int q = tid; q < (P2 >> 2); q += nthr) {
+        const int x0 = q * 4;
+        U4 w{0, 0, 0, 0};
+        if (x0 < m) w = draw(a.seed_lo, a.seed_hi, 0u, (uint32_t)gen, TAG_SELECT, (uint32_t)q);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int x = x0 + t;
+            K[x] = (x < m) ? (((uint64_t)(uint32_t)a.f_all[x] << 48) |
+                              ((uint64_t)word_of(w, t) << 16) | (uint32_t)x)
+                           : ~0ull;
+        }
+    }
+    for (int q = tid; q < nbw; q += nthr) blocked[q] = 0u;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P2; i += nthr) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t x = K[i], y = K[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        K[i] = y;
+                        K[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid >= 64) return;
+    const int lane = tid;
+    int na = 0, nr = 0;
+    bool full = false;
+    for (int base = 0; base < m && !full; base += 64) {
+        const int r = base + lane;
+        const bool valid = r < m;
+        const int x = valid ? (int)(K[r] & 0xFFFFull) : 0;
+        const int d = valid ? a.deg[x] : 0;
+        int pos = 0;
+        while (pos < 64) {
+            const bool blk = valid && ((blocked[x >> 5] >> (x & 31)) & 1u);
+            const bool act = valid && lane >= pos;
+            const uint64_t dep = ballot(act && !blk && d > 0);
+            const int L = dep ? (__ffsll((unsigned long long)dep) - 1) : 64;
+            const bool inr = act && lane < L;
+            const uint64_t accm = ballot(inr && !blk), rejm = ballot(inr && blk);
+            const int room = a.p - na;
+            const uint32_t ra = rank_below(accm);
+            if (inr && !blk && (int)ra < room) a.acc[na + (int)ra] = x;
+            const uint32_t rr = rank_below(rejm);
+            if (inr && blk) a.rej[nr + (int)rr] = x;
+            const int nacc = (int)__popcll(accm);
+            na += nacc < room ? nacc : room;
+            nr += (int)__popcll(rejm);
+            if (na >= a.p) {
+                full = true;
+                break;
+            }
+            if (L == 64) break;
+            const int xL = (int)shfl_u32((uint32_t)x, L), dL = (int)shfl_u32((uint32_t)d, L);
+            if (lane == 0) a.acc[na] = xL;
+            ++na;
+            if (na >= a.p) {
+                full = true;
+                break;
+            }
+            if (dL <= kAdj) {
+                if (lane < dL) {
+                    const int y = a.adj[(size_t)xL * kAdj + lane];
+                    atomicOr(&blocked[y >> 5], 1u << (y & 31));
+                }
+            } else {
+                const int16_t *row = a.D + (size_t)xL * a.ld;
+                for (int y = lane; y < m; y += 64)
+                    if (y != xL && a.spacing * (int64_t)row[y] <= (int64_t)a.nv)
+                        atomicOr(&blocked[y >> 5], 1u << (y & 31));
+            }
+            PLSE_WAVE_SYNC();
+            pos = L + 1;
+        }
+    }
+    // fill rule: rejected candidates in scan order complete a short population
+    PLSE_WAVE_SYNC();
+    for (int t = lane; t < a.p - na; t += 64) a.acc[na + t] = a.rej[t];
+}
+
+size_t select_lds_bytes(int m, int pow2, bool keys_in_lds) {
+    const size_t b = ((size_t)((m + 31) / 32) * 4 + 15) & ~(size_t)15;
+    return b + (keys_in_lds ? (size_t)pow2 * 8 : 0);
+}
+
+hipError_t launch_select(const SelectArgs &a, hipStream_t stream) {
+    const size_t lds = select_lds_bytes(a.m, a.pow2, a.keys_in_lds != 0);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_close(const CloseArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL(close_kernel, dim3((a.m + 3) / 4), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+// New population P_{t+1} = accepted candidates in acceptance order: rows,
+// f, uid ((gen << 32) | slot for members of P'), partner history (empty for
+// members of P').  Written to the tmp arrays, then copied back.
+
+__global__ __launch_bounds__(256) void gather_kernel(const GatherArgs a) {
+    if (a.ctl->stop) return;
+    const int r = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (r >= a.p) return;
+    const int lane = lane_id();
+    const int x = min(max(a.acc[r], 0), 2 * a.p - 1);
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.S_all + (size_t)x * a.stride);
+    uint4 *dst = reinterpret_cast<uint4 *>(a.S_tmp + (size_t)r * a.stride);
+    for (int q = lane; q < (a.stride >> 4); q += 64) dst[q] = src[q];
+    const bool old = x < a.p;
+    if (lane == 0) {
+        a.f_tmp[r] = a.f_all[x];
+        a.uid_tmp[r] = old ? a.uid[x] : (((uint64_t)(uint32_t)a.ctl->gen << 32) | (uint32_t)(x - a.p));
+        a.hc_tmp[r] = old ? a.hc[x] : 0;
+    }
+    if (old) a.hist_tmp[(size_t)r * kHist + lane] = a.hist[(size_t)x * kHist + lane];
+}
+
+__global__ __launch_bounds__(256) void copyback_kernel(const GatherArgs a) {
+    if (a.ctl->stop) return;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t nq = (size_t)a.p * (a.stride >> 4);
+    uint4 *S = reinterpret_cast<uint4 *>(const_cast<uint8_t *>(a.S_all));
+    for (size_t q = t; q < nq; q += (size_t)gridDim.x * blockDim.x)
+        S[q] = reinterpret_cast<const uint4 *>(a.S_tmp)[q];
+    uint64_t *hist = const_cast<uint64_t *>(a.hist);
+    for (size_t q = t; q < (size_t)a.p * kHist; q += (size_t)gridDim.x * blockDim.x)
+        hist[q] = a.hist_tmp[q];
+    if (t < (size_t)a.p) {
+        const_cast<int32_t *>(a.f_all)[t] = a.f_tmp[t];
+        const_cast<uint64_t *>(a.uid)[t] = a.uid_tmp[t];
+        const_cast<int32_t *>(a.hc)[t] = a.hc_tmp[t];
+    }
+}
+
+hipError_t launch_gather(const GatherArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL(gather_kernel, dim3((a.p + 3) / 4), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(copyback_kernel, dim3(1024), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Parent matching (Section 3.5.1): nearest neighbour (D, then slot) among the
+// individuals not yet crossed with S_i; plain nearest neighbour when all are.
+// uid -> slot through an open-addressing table rebuilt every generation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t hash_uid(uint64_t u) {
+    u ^= u >> 33;
+    u *= 0xFF51AFD7ED558CCDull;
+    u ^= u >> 33;
+    return (uint32_t)u;
+}
+
+
+__global__ void hash_clear_kernel(const HashArgs a) {
+    if (a.ctl && a.ctl->stop) return;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    for (int q = t; q < a.hsize; q += gridDim.x * blockDim.x) a.hkeys[q] = ~0ull;
+}
+
+__global__ void hash_insert_kernel(const HashArgs a) {
+    if (a.ctl && a.ctl->stop) return;
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= a.p) return;
+    const uint64_t u = a.uid[i];
+    uint32_t h = hash_uid(u) & (uint32_t)(a.hsize - 1);
+    for (;;) {
+        const unsigned long long prev =
+            atomicCAS((unsigned long long *)&a.hkeys[h], ~0ull, (unsigned long long)u);
+        if (prev == ~0ull || prev == u) {
+            a.hvals[h] = i;
+            return;
+        }
+        h = (h + 1) & (uint32_t)(a.hsize - 1);
+    }
+}
+
+
+__global__ __launch_bounds__(256) void match_kernel(const MatchArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    if (a.ctl && a.ctl->stop) return;
+    const int wv = (int)(threadIdx.x >> 6), lane = lane_id();
+    const int i = (int)blockIdx.x * 4 + wv;
+    const int nbw = (a.p + 31) / 32;
+    uint32_t *excl = reinterpret_cast<uint32_t *>(lds) + (size_t)wv * nbw;
+    if (i >= a.p) return;
+    for (int q = lane; q < nbw; q += 64) excl[q] = 0u;
+    PLSE_WAVE_SYNC();
+    const int hcount = max(a.hc[i], 0);
+    const int nh = min(hcount, a.hist_len);
+    for (int t = lane; t < nh; t += 64) {
+        const uint64_t u = a.hist[(size_t)i * kHist + t];
+        uint32_t h = hash_uid(u) & (uint32_t)(a.hsize - 1);
+        for (;;) {
+            const uint64_t k = a.hkeys[h];
+            if (k == u) {
+                const int s = a.hvals[h];
+                atomicOr(&excl[s >> 5], 1u << (s & 31));
+                break;
+            }
+            if (k == ~0ull) break;
+            h = (h + 1) & (uint32_t)(a.hsize - 1);
+        }
+    }
+    PLSE_WAVE_SYNC();
+    const int ai = a.idx ? a.idx[i] : i;
+    const int16_t *row = a.D + (size_t)ai * a.ld;
+    uint64_t best = ~0ull;
+    for (int pass = 0; pass < 2 && best == ~0ull; ++pass) {
+        uint64_t lb = ~0ull;
+        for (int j = lane; j < a.p; j += 64) {
+            if (j == i) continue;
+            if (pass == 0 && ((excl[j >> 5] >> (j & 31)) & 1u)) continue;
+            const int aj = a.idx ? a.idx[j] : j;
+            const uint64_t key = ((uint64_t)(uint16_t)row[aj] << 32) | (uint32_t)j;
+            lb = key < lb ? key : lb;
+        }
+        best = wave_min_u64(lb);
+    }
+    if (lane == 0) {
+        const int j = (int)(uint32_t)best;
+        a.partner[i] = j;
+        a.dpart[i] = (int32_t)(best >> 32);
+        if (a.hist_len > 0) {
+            const int pos = hcount % a.hist_len;
+            a.hist[(size_t)i * kHist + pos] = a.uid[j];
+            int nc = hcount + 1;
+            if (nc >= 2 * a.hist_len) nc -= a.hist_len;
+            a.hc[i] = nc;
+        }
+    }
+}
+
+hipError_t launch_match(const HashArgs &h, const MatchArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL(hash_clear_kernel, dim3((h.hsize + 255) / 256), dim3(256), 0, stream, h);
+    hipLaunchKernelGGL(hash_insert_kernel, dim3((h.p + 255) / 256), dim3(256), 0, stream, h);
+    const size_t lds = (size_t)4 * ((a.p + 31) / 32) * 4;
+    hipLaunchKernelGGL(match_kernel, dim3((a.p + 3) / 4), dim3(256), lds, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// AUX crossover (Alg. 5): vertex v keeps S_i(v) when its XOVER draw is below
+// thr = floor((beta*D - |V|) 2^32 / (beta*D)) (p_ij of Eq. 9 in 2^-32
+// units; 0 when beta*D <= |V|), else takes S_j(v).  One wave per child, four
+// vertices per lane step (one Philox block).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void aux_kernel(const AuxArgs a) {
+    int gen = a.gen_fixed;
+    if (gen == 0) {
+        if (a.ctl->stop) return;
+        gen = a.ctl->gen;
+    }
+    const int i = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (i >= a.p) return;
+    const int lane = lane_id();
+    int j = a.partner[i];
+    if (j < 0 || j >= a.p) j = i;  // out-of-range partner: no crossover
+    const uint64_t bd = (uint64_t)a.beta_num * (uint64_t)(uint32_t)a.dpart[i];
+    const uint64_t bv = (uint64_t)a.beta_den * (uint64_t)a.nv;
+    const uint64_t thr = (bd <= bv) ? 0ull : (((bd - bv) << 32) / bd);
+    const uint32_t *si = reinterpret_cast<const uint32_t *>(a.S + (size_t)i * a.stride);
+    const uint32_t *sj = reinterpret_cast<const uint32_t *>(a.S + (size_t)j * a.stride);
+    uint32_t *so = reinterpret_cast<uint32_t *>(a.S_off + (size_t)i * a.stride);
+    const int nq = a.stride >> 2;
+    for (int q = lane; q < nq; q += 64) {
+        uint32_t out = 0u;
+        if (4 * q < a.nv) {
+            const U4 w = draw(a.seed_lo, a.seed_hi, (uint32_t)i, (uint32_t)gen, TAG_XOVER,
+                              (uint32_t)q);
+            const uint32_t x = si[q], y = sj[q];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (4 * q + t < a.nv) {
+                    const uint32_t b = ((uint64_t)word_of(w, t) < thr) ? x : y;
+                    out |= b & (0xFFu << (8 * t));
+                }
+            }
+        }
+        so[q] = out;
+    }
+}
+
+hipError_t launch_aux(const AuxArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL(aux_kernel, dim3((a.p + 3) / 4), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_best(const BestArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t stream) {
+    hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, stream, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_begin(Ctl *ctl, hipStream_t stream) {
+    hipLaunchKernelGGL(gen_begin_kernel, dim3(1), dim3(64), 0, stream, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_pop_setup(int p, int stride, uint64_t *uid, int32_t *hc, const uint8_t *S,
+                            uint8_t *S_off, hipStream_t stream) {
+    hipLaunchKernelGGL(pop_setup_kernel, dim3(1024), dim3(256), 0, stream, p, stride, uid, hc, S,
+                       S_off);
+    return hipGetLastError();
+}
+
+hipError_t evo_set_lds_limit(int bytes) {
+    hipError_t e = hipFuncSetAttribute((const void *)select_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)match_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace plse

@@ -1,0 +1,152 @@
+// kernels.h -- argument blocks and launch entry points of the libplse HIP
+// kernels (gfx950), shared by the kernels and the host orchestrator.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "plse_internal.h"
+
+namespace plse {
+
+struct PlitsArgs {
+    DevInstance I;
+    Params P;
+    const uint8_t *S_in;   // [p][stride]
+    uint8_t *S_out;        // [p][stride]
+    int32_t *f_out;        // [p]
+    uint64_t *cnt_out;     // [p][kCounters]
+    void *conf;            // [p][nd] of ConfT
+    uint32_t *tabu;        // [p][nd + nv]
+    const Ctl *ctl;        // generation and stop flag when gen_fixed == 0
+    int32_t gen_fixed;
+    int32_t p;
+    uint32_t seed_lo, seed_hi;
+    int32_t lds_per_wave;
+    int32_t off_cs, off_bm, off_scr;
+};
+
+struct InitArgs {
+    DevInstance I;
+    uint8_t *S;            // [p][stride] out
+    int32_t *f;            // [p] out
+    int32_t p;
+    int32_t pow2;          // power of two >= nv (sort size)
+    uint32_t seed_lo, seed_hi;
+};
+
+struct BestArgs {
+    Ctl *ctl;
+    GenStat *stats;          // [max generations]
+    const int32_t *f_new;    // [p]
+    const uint8_t *S_new;    // [p][stride]
+    const uint64_t *cnt;     // [p][kCounters]
+    uint8_t *Sstar;          // [stride]
+    int32_t p, stride, nsq_minus_l, ub, stop_at_ub;
+};
+
+struct PackArgs {
+    const Ctl *ctl;
+    const uint8_t *S;        // [m][stride]
+    uint32_t *planes;        // [m][W][B]
+    int32_t m, nv, stride, W, B;
+};
+
+struct DistArgs {
+    const Ctl *ctl;
+    const uint32_t *planes;  // [m][W][B]
+    int16_t *D;              // [m][ld]
+    int32_t m, W, ld, ntiles;
+};
+
+struct CloseArgs {
+    const Ctl *ctl;
+    const int16_t *D;
+    int32_t *deg;
+    uint16_t *adj;           // [m][kAdj]
+    int32_t m, ld, nv;
+    int64_t spacing;
+};
+
+struct SelectArgs {
+    const Ctl *ctl;
+    const int32_t *f_all;    // [m]
+    const int16_t *D;        // [m][ld]
+    const int32_t *deg;
+    const uint16_t *adj;
+    uint64_t *keys_g;        // [pow2] global scratch (when not in LDS)
+    int32_t *rej;            // [m] scratch
+    int32_t *acc;            // [p] out
+    int32_t p, m, ld, nv, pow2, keys_in_lds, gen_fixed;
+    int64_t spacing;
+    uint32_t seed_lo, seed_hi;
+};
+
+struct GatherArgs {
+    const Ctl *ctl;
+    const int32_t *acc;
+    const uint8_t *S_all;    // [2p][stride]
+    const int32_t *f_all;    // [2p]
+    const uint64_t *uid;     // [p]
+    const uint64_t *hist;    // [p][kHist]
+    const int32_t *hc;       // [p]
+    uint8_t *S_tmp;
+    int32_t *f_tmp;
+    uint64_t *uid_tmp, *hist_tmp;
+    int32_t *hc_tmp;
+    int32_t p, stride;
+};
+
+struct HashArgs {
+    const Ctl *ctl;
+    const uint64_t *uid;     // [p]
+    uint64_t *hkeys;         // [hsize]
+    int32_t *hvals;
+    int32_t p, hsize;
+};
+
+struct MatchArgs {
+    const Ctl *ctl;
+    const int16_t *D;        // distances, row/col through idx (identity if null)
+    const int32_t *idx;
+    const uint64_t *uid;
+    uint64_t *hist;          // [p][kHist]
+    int32_t *hc;
+    const uint64_t *hkeys;
+    const int32_t *hvals;
+    int32_t *partner, *dpart;
+    int32_t p, ld, hsize, hist_len;
+};
+
+struct AuxArgs {
+    const Ctl *ctl;
+    const uint8_t *S;        // [p][stride]
+    const int32_t *partner, *dpart;
+    uint8_t *S_off;          // [p][stride]
+    int32_t p, nv, stride, gen_fixed;
+    int64_t beta_num, beta_den;
+    uint32_t seed_lo, seed_hi;
+};
+
+hipError_t launch_plits(const PlitsArgs &a, int conf_bytes, int waves_per_block,
+                        hipStream_t stream);
+hipError_t plits_set_lds_limit(int bytes);
+hipError_t launch_init(const InitArgs &a, hipStream_t stream);
+size_t init_lds_bytes(const DevInstance &I, int pow2);
+hipError_t init_set_lds_limit(int bytes);
+hipError_t launch_best(const BestArgs &a, hipStream_t stream);
+hipError_t launch_distances(const Ctl *ctl, const uint8_t *S, uint32_t *planes, int16_t *D,
+                            int m, int nv, int stride, int ld, int B, hipStream_t stream);
+hipError_t launch_close(const CloseArgs &a, hipStream_t stream);
+hipError_t launch_select(const SelectArgs &a, hipStream_t stream);
+size_t select_lds_bytes(int m, int pow2, bool keys_in_lds);
+hipError_t launch_gather(const GatherArgs &a, hipStream_t stream);
+hipError_t launch_match(const HashArgs &h, const MatchArgs &a, hipStream_t stream);
+hipError_t launch_aux(const AuxArgs &a, hipStream_t stream);
+hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t stream);
+hipError_t launch_gen_begin(Ctl *ctl, hipStream_t stream);
+hipError_t launch_pop_setup(int p, int stride, uint64_t *uid, int32_t *hc, const uint8_t *S,
+                            uint8_t *S_off, hipStream_t stream);
+hipError_t evo_set_lds_limit(int bytes);
+
+}  // namespace plse

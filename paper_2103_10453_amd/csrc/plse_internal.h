@@ -1,0 +1,66 @@
+// plse_internal.h -- structures shared by the host orchestrator and the HIP
+// kernels of libplse (gfx950).  Plain data only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace plse {
+
+constexpr int kHist = 64;        // partner-history slots per individual
+constexpr int kCounters = 8;     // iters, moves, idle, cands, elig, nupd, snaps, repairs
+constexpr int kAdj = 32;         // close-neighbour list capacity per candidate (select)
+constexpr uint8_t kNoSlot = 0xFF;
+
+enum Counter { C_ITERS = 0, C_MOVES, C_IDLE, C_CANDS, C_ELIG, C_NUPD, C_SNAPS, C_REPAIRS };
+
+// Random-stream tags: which decision a Philox draw belongs to.
+enum Tag : uint32_t {
+    TAG_INIT_ORDER = 0x01,
+    TAG_INIT_PICK = 0x02,
+    TAG_PLITS1 = 0x11,
+    TAG_PLITS2 = 0x12,
+    TAG_SELECT = 0x21,
+    TAG_XOVER = 0x31,
+};
+
+// Reduced graph of one instance, as device pointers into the workspace.
+struct DevInstance {
+    int32_t n, nv, nd, stride;       // order, |V|, sum |D*(v)|, row stride (bytes)
+    int32_t l, ub;
+    const uint8_t *vrow, *vcol;      // [nv]
+    const uint32_t *doff;            // [nv+1] D*(v) = dom[doff[v] .. doff[v+1])
+    const uint8_t *dom;              // [nd] colours, ascending
+    const uint8_t *slot;             // [nv*(n+1)] slot of colour k in D*(v), kNoSlot if absent
+    const uint16_t *rowv, *colv;     // [n*n] vertices of row r at r*n + t
+    const uint8_t *rowc, *colc;      // [n] vertex counts per row / column
+    const uint64_t *dmask;           // [nv*2] D*(v) as a 128-bit colour mask
+};
+
+struct Params {
+    int64_t depth1, depth2;
+    int64_t alpha_num, alpha_den;
+    int64_t beta_num, beta_den;
+    int64_t spacing;
+    int32_t stop_at_ub;
+    int32_t hist_len;
+};
+
+// Device control block of a solve (one per handle).
+struct Ctl {
+    int32_t gen;          // current generation (1-based once started)
+    int32_t stop;         // set when the bound is reached with stop_at_ub
+    int32_t fstar;        // best f so far (INT32_MAX before generation 1)
+    int32_t best_gen;
+    int32_t gens_run;
+    int32_t pad[3];
+};
+
+// Per-generation record.
+struct GenStat {
+    int32_t best_f;
+    int32_t pad;
+    uint64_t cnt[kCounters];
+};
+
+}  // namespace plse

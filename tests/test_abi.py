@@ -1,0 +1,107 @@
+"""C-ABI library: loads, exports every symbol include/plse.h declares, and its
+host-side logic (Alg. 1 preprocessing, bound, parameters, workspace planning,
+error paths) agrees with the oracle.  No GPU call is made here."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_10453_amd import instances as gen
+from paper_2103_10453_amd import plse as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "plse.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(plse_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    lib = ctypes.CDLL(P.library_path())
+    names = _declared()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(P.exported_symbols())
+
+
+def test_library_is_gfx950_code():
+    out = open(P.library_path(), "rb").read()
+    assert b"gfx950" in out
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_preprocessing_matches_oracle(oracle_mod, case):
+    n = [3, 4, 5, 10, 20, 50, 70, 100, 7, 30][case]
+    r = [0.3, 0.5, 0.6, 0.4, 0.7, 0.5, 0.3, 0.6, 0.9, 0.8][case]
+    g = gen.planted(n, r, case) if case % 2 else gen.random_greedy(n, r, case)
+    h = P.plse_create(g)
+    try:
+        I = oracle_mod.Instance(g)
+        assert P.plse_info(h) == (I.nv, I.l, I.ub)
+        assert P.plse_row_stride(h) % 16 == 0 and P.plse_row_stride(h) >= I.nv
+    finally:
+        P.plse_destroy(h)
+
+
+def test_n3_example_bound():
+    h = P.plse_create(np.array([[1, 0, 0], [2, 0, 0], [0, 0, 3]]))
+    assert P.plse_info(h) == (5, 1, 7)
+    P.plse_destroy(h)
+
+
+def test_invalid_grids_and_arguments():
+    for bad in ([[1, 1], [0, 0]], [[1, 0], [1, 0]], [[3, 0], [0, 0]], [[-1, 0], [0, 0]]):
+        with pytest.raises(P.PlseError) as e:
+            P.plse_create(np.array(bad))
+        assert e.value.status == P.PLSE_E_GRID
+    with pytest.raises(P.PlseError) as e:
+        P.plse_create(np.zeros((128, 128), dtype=np.int8))
+    assert e.value.status == P.PLSE_E_ARG
+
+
+def test_parameters_and_defaults():
+    g = gen.planted(10, 0.4, 0)
+    h = P.plse_create(g)
+    try:
+        assert P.plse_get_param(h, "depth") == 1000
+        assert (P.plse_get_param(h, "depth1"), P.plse_get_param(h, "depth2")) == (880, 120)
+        assert P.plse_get_param(h, "alpha_num") == 6 and P.plse_get_param(h, "alpha_den") == 10
+        assert P.plse_get_param(h, "beta_num") == 20 and P.plse_get_param(h, "spacing") == 10
+        assert P.plse_get_param(h, "nn_history") == 64
+        P.plse_set_param(h, "depth", 50)
+        assert (P.plse_get_param(h, "depth1"), P.plse_get_param(h, "depth2")) == (0, 50)
+        for key, val in (("nope", 1), ("conf_bytes", 3), ("nn_history", 65), ("alpha_den", 0),
+                         ("waves_per_block", 3)):
+            with pytest.raises(P.PlseError) as e:
+                P.plse_set_param(h, key, val)
+            assert e.value.status == P.PLSE_E_PARAM
+    finally:
+        P.plse_destroy(h)
+
+
+def test_workspace_planning_and_missing_workspace():
+    g = gen.planted(50, 0.5, 1000)
+    h = P.plse_create(g)
+    try:
+        b1 = P.plse_workspace_bytes(h, 1024)
+        b2 = P.plse_workspace_bytes(h, 16384)
+        assert b2 > b1 > 0
+        # the 2p x 2p int16 distance matrix dominates at large p
+        assert b2 >= (2 * 16384) ** 2 * 2
+        with pytest.raises(P.PlseError) as e:
+            P.plse_solve(h, 50, 64, 1, 1, stream=0)
+        assert e.value.status == P.PLSE_E_WORKSPACE
+        with pytest.raises(P.PlseError) as e:
+            P.plse_workspace_bytes(h, 1)
+        assert e.value.status == P.PLSE_E_ARG
+        with pytest.raises(P.PlseError) as e:
+            P.plse_workspace_bytes(h, 40000)
+        assert e.value.status == P.PLSE_E_ARG
+    finally:
+        P.plse_destroy(h)
