@@ -139,4 +139,15 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *total) 
 
 __device__ __forceinline__ int readfirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Allow a kernel the device's per-block LDS minus its own static LDS as
+// dynamic shared memory.
+inline hipError_t set_dynamic_lds_limit(const void *fn, int device_max) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return e;
+    const int dyn = device_max - (int)attr.sharedSizeBytes;
+    if (dyn <= 0) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+}
+
 }  // namespace plse

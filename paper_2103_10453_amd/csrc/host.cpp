@@ -89,38 +89,41 @@ namespace {
 
 thread_local std::string g_hip_error;
 
-int hip_fail(hipError_t e) {
+int hip_fail(hipError_t e, const char *what = nullptr) {
     g_hip_error = hipGetErrorString(e);
+    if (what) g_hip_error += std::string(" in ") + what;
     return PLSE_E_HIP;
 }
 
-#define HIP_TRY(x)                                  \
-    do {                                            \
-        hipError_t e_ = (x);                        \
-        if (e_ != hipSuccess) return hip_fail(e_);  \
+#define HIP_TRY(x)                                      \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #x);  \
     } while (0)
 
 std::once_flag g_attr_once;
-hipError_t g_attr_err = hipSuccess;
+int g_lds_limit = 65536;  // dynamic LDS per block every kernel may use
 
+// Raise the dynamic-LDS limit of the kernels to the device's per-block LDS.
+// If the runtime refuses, kernels keep the default 64 KiB and launch shapes
+// are chosen within it.
 void set_attributes_once() {
     std::call_once(g_attr_once, [] {
         int dev = 0, lds = 65536;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        hipError_t e = plits_set_lds_limit(lds);
-        if (e == hipSuccess) e = init_set_lds_limit(lds);
-        if (e == hipSuccess) e = evo_set_lds_limit(lds);
-        g_attr_err = e;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess)
+            lds = 65536;
+        if (lds > 65536 && plits_set_lds_limit(lds) == hipSuccess &&
+            init_set_lds_limit(lds) == hipSuccess && evo_set_lds_limit(lds) == hipSuccess)
+            g_lds_limit = lds - 1024;  // headroom for the kernels' static LDS
+        else
+            g_lds_limit = 65536 - 1024;
+        (void)hipGetLastError();
     });
 }
 
-int max_lds_per_block() {
-    int dev = 0, lds = 65536;
-    if (hipGetDevice(&dev) == hipSuccess)
-        (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    return lds;
-}
+int max_lds_per_block() { return g_lds_limit; }
 
 // PLITS per-wave LDS: S, current slot, eligibility bitmap, scratch (eligible
 // list or the row/column histograms, whichever is larger).
@@ -436,7 +439,6 @@ int check_ws(plse_instance *h, int p, Layout *L) {
     *L = plan(h, p);
     if (!h->ws || h->ws_bytes < L->total) return PLSE_E_WORKSPACE;
     set_attributes_once();
-    if (g_attr_err != hipSuccess) return hip_fail(g_attr_err);
     return PLSE_OK;
 }
 

@@ -596,11 +596,9 @@ hipError_t launch_pop_setup(int p, int stride, uint64_t *uid, int32_t *hc, const
 }
 
 hipError_t evo_set_lds_limit(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)select_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = set_dynamic_lds_limit((const void *)select_kernel, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)match_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return set_dynamic_lds_limit((const void *)match_kernel, bytes);
 }
 
 }  // namespace plse

@@ -117,7 +117,6 @@ hipError_t launch_init(const InitArgs &a, hipStream_t stream) {
 
 namespace plse {
 hipError_t init_set_lds_limit(int bytes) {
-    return hipFuncSetAttribute((const void *)init_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               bytes);
+    return set_dynamic_lds_limit((const void *)init_kernel, bytes);
 }
 }  // namespace plse

@@ -409,11 +409,9 @@ hipError_t launch_plits(const PlitsArgs &a, int conf_bytes, int waves_per_block,
 }
 
 hipError_t plits_set_lds_limit(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)plits_kernel<uint8_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = set_dynamic_lds_limit((const void *)plits_kernel<uint8_t>, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)plits_kernel<int16_t>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return set_dynamic_lds_limit((const void *)plits_kernel<int16_t>, bytes);
 }
 
 }  // namespace plse
