@@ -7,9 +7,9 @@ HBM before the timed region; W warmup generations run first, then exactly K
 generations are timed (device synchronised on both sides).
 
 value = tabu moves executed in the K timed generations / their wall time.
-roofline: the tabu-search kernel's algorithmic HBM bytes per launch (from the
-per-generation counters, see plits_hbm_bytes) over its mean launch time from
-HIP events recorded on the launch stream.
+roofline: the tabu-search kernel's algorithmic state bytes per launch (from
+the per-generation counters, see plits_state_bytes; the state is LDS-resident)
+over its mean launch time from HIP events recorded on the launch stream.
 cpu_baseline: the CPU oracle's PLITS on a bounded sample of the same
 generation-1 population, on the host's cores.
 """
@@ -27,23 +27,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 256 CUs x 128 B/clk x 2.4 GHz (nominal; the level that holds the state)
+LDS_PEAK_GBS = 256 * 128 * 2.4
 
 
-def plits_hbm_bytes(cnt, p, nv, nd, conf_bytes, tabu_bytes=4):
-    """Algorithmic HBM bytes of one tabu-search launch (one generation).
+def plits_state_bytes(cnt, p, n, nv):
+    """Algorithmic bytes of search state one tabu-search launch touches.
 
-    Per iteration each candidate one-move reads its conflict entry and its tabu
-    entry; each move read-modify-writes the conflict entries of the moved
-    vertex's neighbours and writes one tabu entry; each snapshot writes |V|
-    bytes.  Each of the two phases of every individual rebuilds its conflict
-    table, clears its tabu table and reads its start row.
+    The state of an individual is its colouring S (1 B per vertex), the row and
+    column colour counts (1 B each), the eligibility bitmap and the tabu table.
+    Per iteration: the bitmap (|V|/8 B); per eligible vertex its colour and
+    the two counts of that colour (3 B); per candidate move the two counts of
+    the candidate colour (2 B).  Per move: four counts read and written (8 B),
+    the colour (1 B), one tabu entry (4 B) and the colours of the 2(n-1) row
+    and column vertices (2(n-1) B).  Per snapshot |V| B; per phase of every
+    individual the start row (|V| B).
     cnt: counters [iters, moves, idle, cands, elig, nupd, snaps, repairs].
     """
-    cands, moves, nupd, snaps = int(cnt[3]), int(cnt[1]), int(cnt[5]), int(cnt[6])
-    per_move = cands * (conf_bytes + tabu_bytes) + nupd * 2 * conf_bytes + moves * tabu_bytes \
-        + snaps * nv
-    setup = p * 2 * (nd * conf_bytes + (nd + nv) * tabu_bytes + nv)
-    return per_move + setup
+    iters, moves, cands, elig, snaps = (int(cnt[0]), int(cnt[1]), int(cnt[3]), int(cnt[4]),
+                                        int(cnt[6]))
+    return (iters * ((nv + 7) // 8) + elig * 3 + cands * 2 + moves * (13 + 2 * (n - 1))
+            + snaps * nv + p * 2 * nv)
 
 
 def cpu_baseline(grid, seed, depth, target_s=12.0):
@@ -81,7 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n50", choices=["n50", "n70_30", "n70_50", "n70_70",
                                                          "small"])
-    ap.add_argument("--conf-bytes", type=int, default=2)
+    ap.add_argument("--lanes-per-vertex", type=int, default=0)
     ap.add_argument("--population", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -110,7 +114,7 @@ def main():
         w["population"] = args.population
     p = w["population"]
     torch.cuda.set_device(0)
-    s = plse.Solver(w["grid"], depth=w["depth"], conf_bytes=args.conf_bytes)
+    s = plse.Solver(w["grid"], depth=w["depth"], lanes_per_vertex=args.lanes_per_vertex)
     s.ensure_workspace(p)
     stream = torch.cuda.current_stream()
 
@@ -130,8 +134,7 @@ def main():
     moves_timed = int(cnt[timed, 1].sum())
     wall = t1 - t0
     value = moves_timed / wall
-    bytes_gen = [plits_hbm_bytes(cnt[g], p, s.nv, s.nd, args.conf_bytes)
-                 for g in range(timed.start, timed.stop)]
+    bytes_gen = [plits_state_bytes(cnt[g], p, s.n, s.nv) for g in range(timed.start, timed.stop)]
     t_plits = [float(ms_plits[g]) for g in range(timed.start, timed.stop)]
     achieved = (sum(bytes_gen) / max(len(bytes_gen), 1)) / (np.mean(t_plits) * 1e-3) / 1e9
     out = {
@@ -149,11 +152,12 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": desc, "n": int(w["grid"].shape[0]), "population": p,
-                   "depth": int(w["depth"]), "conf_bytes": args.conf_bytes,
+                   "depth": int(w["depth"]),
+                   "lanes_per_vertex": int(s.get_param("lanes_per_vertex")),
                    "vertices": s.nv, "sum_domain": s.nd,
                    "waves_per_block": int(s.get_param("waves_per_block"))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": None},
         "detail": {"moves_timed": moves_timed, "plits_ms_per_gen": t_plits,
                    "rest_ms_per_gen": [float(ms_rest[g]) for g in range(timed.start, timed.stop)],
                    "plits_bytes_per_gen": bytes_gen,

@@ -362,15 +362,12 @@ static void plits_phase(const inst_t *I, const int64_t *P, uint64_t seed, uint32
         int64_t dc = (bk ? W->conf[(size_t)bv * (n + 1) + bk] : 0) -
                      (old ? W->conf[(size_t)bv * (n + 1) + old] : 0);
         FOR_NEIGHBOURS(I, bv, u, {
-            if (old) {
-                W->conf[(size_t)u * (n + 1) + old]--;
-                if (I->in_dom[(size_t)u * (n + 1) + old]) cnt[ORC_C_NUPD]++;
-            }
-            if (bk) {
-                W->conf[(size_t)u * (n + 1) + bk]++;
-                if (I->in_dom[(size_t)u * (n + 1) + bk]) cnt[ORC_C_NUPD]++;
-            }
+            if (old) W->conf[(size_t)u * (n + 1) + old]--;
+            if (bk) W->conf[(size_t)u * (n + 1) + bk]++;
         });
+        /* work counter: the move changes the row and column counts of the
+         * colour it leaves and of the colour it takes */
+        cnt[ORC_C_NUPD] += 2u * (old != 0) + 2u * (bk != 0);
         S[bv] = (uint8_t)bk;
         f += (bk == 0) - (old == 0);
         c += dc;

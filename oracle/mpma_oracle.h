@@ -59,7 +59,8 @@ enum {
     ORC_C_IDLE,         /* iterations with no admissible candidate               */
     ORC_C_CANDS,        /* candidate one-moves examined                          */
     ORC_C_ELIG,         /* eligible vertices, summed over iterations             */
-    ORC_C_NUPD,         /* conflict-table entries changed by moves               */
+    ORC_C_NUPD,         /* row/column colour counts changed by moves (2 per      */
+                        /* coloured end of a move: colour left, colour taken)    */
     ORC_C_SNAPS,        /* best-solution snapshots                               */
     ORC_C_REPAIRS,      /* vertices uncoloured by the final repair               */
     ORC_NCOUNTERS

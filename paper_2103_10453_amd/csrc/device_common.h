@@ -139,6 +139,78 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *total) 
 
 __device__ __forceinline__ int readfirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// ---------------------------------------------------------------------------
+// DPP forms of the collectives: cross-lane moves inside the VALU instead of
+// LDS permutes.  Reduction order: quad swaps, half-row and row mirrors, then
+// row broadcasts 15 and 31, after which lane 63 holds the wave result.
+// ---------------------------------------------------------------------------
+enum : int {
+    DPP_QUAD_1032 = 0xB1,     // quad_perm [1,0,3,2]
+    DPP_QUAD_2301 = 0x4E,     // quad_perm [2,3,0,1]
+    DPP_ROW_SHR1 = 0x111,
+    DPP_ROW_SHR2 = 0x112,
+    DPP_ROW_SHR4 = 0x114,
+    DPP_ROW_SHR8 = 0x118,
+    DPP_ROW_MIRROR = 0x140,
+    DPP_ROW_HALF_MIRROR = 0x141,
+    DPP_ROW_BCAST15 = 0x142,
+    DPP_ROW_BCAST31 = 0x143,
+};
+
+template <int CTRL, int ROW_MASK = 0xF, bool BOUND_ZERO = false>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, BOUND_ZERO);
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_min_step(uint32_t &hi, uint32_t &lo) {
+    const uint32_t oh = dpp_u32<CTRL, ROW_MASK>(hi, hi);
+    const uint32_t ol = dpp_u32<CTRL, ROW_MASK>(lo, lo);
+    const bool take = (oh < hi) || (oh == hi && ol < lo);
+    hi = take ? oh : hi;
+    lo = take ? ol : lo;
+}
+
+// Wave minimum of a 64-bit key, returned uniformly to all lanes.
+__device__ __forceinline__ uint64_t wave_min_u64_dpp(uint64_t v) {
+    uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+    dpp_min_step<DPP_QUAD_1032, 0xF>(hi, lo);
+    dpp_min_step<DPP_QUAD_2301, 0xF>(hi, lo);
+    dpp_min_step<DPP_ROW_HALF_MIRROR, 0xF>(hi, lo);
+    dpp_min_step<DPP_ROW_MIRROR, 0xF>(hi, lo);
+    dpp_min_step<DPP_ROW_BCAST15, 0xA>(hi, lo);
+    dpp_min_step<DPP_ROW_BCAST31, 0xC>(hi, lo);
+    return ((uint64_t)readlane_u32(hi, 63) << 32) | readlane_u32(lo, 63);
+}
+
+// Wave sum (u32), returned uniformly.
+__device__ __forceinline__ uint32_t wave_sum_u32_dpp(uint32_t x) {
+    x += dpp_u32<DPP_QUAD_1032>(0u, x);
+    x += dpp_u32<DPP_QUAD_2301>(0u, x);
+    x += dpp_u32<DPP_ROW_HALF_MIRROR>(0u, x);
+    x += dpp_u32<DPP_ROW_MIRROR>(0u, x);
+    x += dpp_u32<DPP_ROW_BCAST15, 0xA>(0u, x);
+    x += dpp_u32<DPP_ROW_BCAST31, 0xC>(0u, x);
+    return readlane_u32(x, 63);
+}
+
+// Exclusive prefix sum (u32) over the wave; *total receives the wave sum.
+__device__ __forceinline__ uint32_t wave_excl_scan_dpp(uint32_t v, uint32_t *total) {
+    uint32_t x = v;
+    x += dpp_u32<DPP_ROW_SHR1, 0xF, true>(0u, x);
+    x += dpp_u32<DPP_ROW_SHR2, 0xF, true>(0u, x);
+    x += dpp_u32<DPP_ROW_SHR4, 0xF, true>(0u, x);
+    x += dpp_u32<DPP_ROW_SHR8, 0xF, true>(0u, x);
+    x += dpp_u32<DPP_ROW_BCAST15, 0xA>(0u, x);
+    x += dpp_u32<DPP_ROW_BCAST31, 0xC>(0u, x);
+    *total = readlane_u32(x, 63);
+    return x - v;
+}
+
 // Allow a kernel the device's per-block LDS minus its own static LDS as
 // dynamic shared memory.
 inline hipError_t set_dynamic_lds_limit(const void *fn, int device_max) {

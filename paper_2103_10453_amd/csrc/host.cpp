@@ -37,10 +37,10 @@ int colour_bits(int n) {
 
 // Offsets of every device array of one handle, for a population p.
 struct Layout {
-    size_t vrow, vcol, doff, dom, slot, rowv, colv, rowc, colc, dmask;
+    size_t vrc, vrec, rowl, coll, rowc, colc;
     size_t ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
-    size_t conf, tabu, planes, D, deg, adj, keys, rej, acc, hkeys, hvals, partner, dpart;
+    size_t tabu, planes, D, deg, adj, keys, rej, acc, hkeys, hvals, partner, dpart;
     size_t total;
     int pow2_sel, hsize;
 };
@@ -52,14 +52,14 @@ struct plse_instance {
     std::vector<int8_t> grid;
     std::vector<int> cell_v;  // -1 prefilled, -2 impossible, else vertex id
     // host images of the device instance tables
-    std::vector<uint8_t> vrow, vcol, dom, slot, rowc, colc;
-    std::vector<uint32_t> doff;
-    std::vector<uint16_t> rowv, colv;
-    std::vector<uint64_t> dmask;
+    std::vector<uint16_t> vrc;
+    std::vector<uint32_t> vrec;  // 8 words per vertex
+    std::vector<uint32_t> rowl, coll;
+    std::vector<uint8_t> rowc, colc;
 
     Params P{};
-    int conf_bytes = 1;
-    int wpb = 0;  // 0: automatic
+    int lpv = 0;  // lanes per eligible vertex in PLITS; 0: automatic
+    int wpb = 0;  // waves per block in PLITS; 0: automatic
 
     uint8_t *ws = nullptr;
     size_t ws_bytes = 0;
@@ -125,31 +125,48 @@ void set_attributes_once() {
 
 int max_lds_per_block() { return g_lds_limit; }
 
-// PLITS per-wave LDS: S, current slot, eligibility bitmap, scratch (eligible
-// list or the row/column histograms, whichever is larger).
+// PLITS per-wave LDS: S, row/column colour counts, eligibility bitmap,
+// per-vertex tabu expiry, eligible-vertex list.
 struct PlitsLds {
-    int per_wave, off_cs, off_bm, off_scr;
+    int per_wave, off_h, off_bm, off_tm, off_el;
 };
 
 PlitsLds plits_lds(const plse_instance *h) {
     PlitsLds L;
     const int W = (h->nv + 31) / 32;
-    L.off_cs = h->stride;
-    L.off_bm = 2 * h->stride;
-    L.off_scr = L.off_bm + (int)round_up((size_t)W * 4, 16);
-    const int scr = (int)std::max<size_t>(round_up((size_t)2 * h->nv, 16),
-                                          round_up((size_t)2 * h->n * (h->n + 1), 16));
-    L.per_wave = L.off_scr + scr;
+    L.off_h = h->stride;
+    L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
+    L.off_tm = L.off_bm + (int)round_up((size_t)W * 4, 16);
+    L.off_el = L.off_tm + (int)round_up((size_t)h->nv * 4, 16);
+    L.per_wave = L.off_el + (int)round_up((size_t)h->nv * 2, 16);
     return L;
 }
 
+// Waves per block maximising resident waves per CU under the LDS budget.
 int choose_wpb(const plse_instance *h) {
     if (h->wpb) return h->wpb;
     const int per = plits_lds(h).per_wave;
     const int lim = max_lds_per_block();
-    for (int w : {4, 2, 1})
-        if (w * per <= lim) return w;
-    return 1;
+    int best = 1, best_waves = 0;
+    for (int w : {1, 2, 4}) {
+        if (w * per > lim) continue;
+        const int waves = (lim / (w * per)) * w;
+        if (waves >= best_waves) {
+            best = w;
+            best_waves = waves;
+        }
+    }
+    return best;
+}
+
+// Lanes per eligible vertex: about four domain colours per lane.
+int choose_lpv(const plse_instance *h) {
+    if (h->lpv) return h->lpv;
+    const double mean = h->nv ? (double)h->nd / h->nv : 1.0;
+    if (mean <= 6.0) return 1;
+    if (mean <= 12.0) return 2;
+    if (mean <= 24.0) return 4;
+    return 8;
 }
 
 Layout plan(const plse_instance *h, int p) {
@@ -163,16 +180,12 @@ Layout plan(const plse_instance *h, int p) {
     const size_t nv = h->nv, n = h->n, nd = h->nd, st = h->stride;
     const size_t m = 2 * (size_t)p;
     const int W = (h->nv + 31) / 32, B = colour_bits(h->n);
-    L.vrow = take(nv);
-    L.vcol = take(nv);
-    L.doff = take(4 * (nv + 1));
-    L.dom = take(nd);
-    L.slot = take(nv * (n + 1));
-    L.rowv = take(2 * n * n);
-    L.colv = take(2 * n * n);
+    L.vrc = take(2 * nv);
+    L.vrec = take(32 * nv);
+    L.rowl = take(4 * n * n);
+    L.coll = take(4 * n * n);
     L.rowc = take(n);
     L.colc = take(n);
-    L.dmask = take(16 * nv);
     L.ctl = take(sizeof(Ctl));
     L.stats = take(sizeof(GenStat) * PLSE_MAX_GENERATIONS);
     L.Sstar = take(st);
@@ -188,7 +201,6 @@ Layout plan(const plse_instance *h, int p) {
     L.hc = take(4 * (size_t)p);
     L.hc_tmp = take(4 * (size_t)p);
     L.cnt = take(8 * (size_t)p * kCounters);
-    L.conf = take((size_t)p * nd * h->conf_bytes);
     L.tabu = take((size_t)p * (nd + nv) * 4);
     L.planes = take(m * W * B * 4);
     L.D = take(m * m * 2);
@@ -220,16 +232,12 @@ DevInstance dev_instance(plse_instance *h, const Layout &L) {
     I.stride = h->stride;
     I.l = h->l;
     I.ub = h->ub;
-    I.vrow = at<uint8_t>(h, L.vrow);
-    I.vcol = at<uint8_t>(h, L.vcol);
-    I.doff = at<uint32_t>(h, L.doff);
-    I.dom = at<uint8_t>(h, L.dom);
-    I.slot = at<uint8_t>(h, L.slot);
-    I.rowv = at<uint16_t>(h, L.rowv);
-    I.colv = at<uint16_t>(h, L.colv);
+    I.vrc = at<uint16_t>(h, L.vrc);
+    I.vrec = at<void>(h, L.vrec);
+    I.rowl = at<uint32_t>(h, L.rowl);
+    I.coll = at<uint32_t>(h, L.coll);
     I.rowc = at<uint8_t>(h, L.rowc);
     I.colc = at<uint8_t>(h, L.colc);
-    I.dmask = at<uint64_t>(h, L.dmask);
     return I;
 }
 
@@ -238,16 +246,12 @@ int upload_instance(plse_instance *h, const Layout &L, hipStream_t s) {
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(h->ws + off, src, bytes, hipMemcpyHostToDevice, s);
     };
-    HIP_TRY(put(L.vrow, h->vrow.data(), h->vrow.size()));
-    HIP_TRY(put(L.vcol, h->vcol.data(), h->vcol.size()));
-    HIP_TRY(put(L.doff, h->doff.data(), 4 * h->doff.size()));
-    HIP_TRY(put(L.dom, h->dom.data(), h->dom.size()));
-    HIP_TRY(put(L.slot, h->slot.data(), h->slot.size()));
-    HIP_TRY(put(L.rowv, h->rowv.data(), 2 * h->rowv.size()));
-    HIP_TRY(put(L.colv, h->colv.data(), 2 * h->colv.size()));
+    HIP_TRY(put(L.vrc, h->vrc.data(), 2 * h->vrc.size()));
+    HIP_TRY(put(L.vrec, h->vrec.data(), 4 * h->vrec.size()));
+    HIP_TRY(put(L.rowl, h->rowl.data(), 4 * h->rowl.size()));
+    HIP_TRY(put(L.coll, h->coll.data(), 4 * h->coll.size()));
     HIP_TRY(put(L.rowc, h->rowc.data(), h->rowc.size()));
     HIP_TRY(put(L.colc, h->colc.data(), h->colc.size()));
-    HIP_TRY(put(L.dmask, h->dmask.data(), 8 * h->dmask.size()));
     return PLSE_OK;
 }
 
@@ -261,7 +265,6 @@ PlitsArgs plits_args(plse_instance *h, const Layout &L, int p, int gen_fixed, ui
     a.S_out = S_out;
     a.f_out = f_out;
     a.cnt_out = cnt;
-    a.conf = h->ws + L.conf;
     a.tabu = at<uint32_t>(h, L.tabu);
     a.ctl = ctl;
     a.gen_fixed = gen_fixed;
@@ -270,9 +273,10 @@ PlitsArgs plits_args(plse_instance *h, const Layout &L, int p, int gen_fixed, ui
     a.seed_hi = (uint32_t)(seed >> 32);
     const PlitsLds pl = plits_lds(h);
     a.lds_per_wave = pl.per_wave;
-    a.off_cs = pl.off_cs;
+    a.off_h = pl.off_h;
     a.off_bm = pl.off_bm;
-    a.off_scr = pl.off_scr;
+    a.off_tm = pl.off_tm;
+    a.off_el = pl.off_el;
     return a;
 }
 
@@ -329,7 +333,7 @@ int enqueue_local_search(plse_instance *h, const Layout &L, int p, uint64_t seed
     HIP_TRY(launch_gen_begin(ctl, s));
     PlitsArgs pa = plits_args(h, L, p, 0, seed, at<uint8_t>(h, L.S_off), S_new, f_all + p,
                               at<uint64_t>(h, L.cnt), ctl);
-    HIP_TRY(launch_plits(pa, h->conf_bytes, choose_wpb(h), s));
+    HIP_TRY(launch_plits(pa, choose_lpv(h), choose_wpb(h), s));
     return PLSE_OK;
 }
 
@@ -473,8 +477,9 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
     for (int k = 1; k <= n; ++k) full[k >> 6] |= 1ull << (k & 63);
     h->rowc.assign(n, 0);
     h->colc.assign(n, 0);
-    h->rowv.assign((size_t)n * n, 0);
-    h->colv.assign((size_t)n * n, 0);
+    h->rowl.assign((size_t)n * n, 0);
+    h->coll.assign((size_t)n * n, 0);
+    std::vector<uint64_t> dmask;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             if (grid[i * n + j]) continue;
@@ -487,27 +492,28 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
             }
             const int v = h->nv++;
             h->cell_v[i * n + j] = v;
-            h->vrow.push_back((uint8_t)i);
-            h->vcol.push_back((uint8_t)j);
-            h->dmask.push_back(d0);
-            h->dmask.push_back(d1);
-            h->rowv[(size_t)i * n + h->rowc[i]++] = (uint16_t)v;
-            h->colv[(size_t)j * n + h->colc[j]++] = (uint16_t)v;
+            h->vrc.push_back((uint16_t)(i | (j << 8)));
+            dmask.push_back(d0);
+            dmask.push_back(d1);
+            h->rowl[(size_t)i * n + h->rowc[i]++] = (uint32_t)v | ((uint32_t)j << 16);
+            h->coll[(size_t)j * n + h->colc[j]++] = (uint32_t)v | ((uint32_t)i << 16);
         }
     h->ub = (h->l == 1) ? n * n - 2 : n * n - h->l;
-    h->doff.assign((size_t)h->nv + 1, 0);
-    h->slot.assign((size_t)h->nv * (n + 1), kNoSlot);
+    // vertex records: 128-bit domain mask, first tabu slot (sum of earlier
+    // domain sizes), coordinates
+    h->vrec.assign((size_t)h->nv * 8, 0);
+    uint32_t off = 0;
     for (int v = 0; v < h->nv; ++v) {
-        h->doff[v] = (uint32_t)h->dom.size();
-        int j = 0;
-        for (int k = 1; k <= n; ++k)
-            if ((h->dmask[2 * v + (k >> 6)] >> (k & 63)) & 1ull) {
-                h->dom.push_back((uint8_t)k);
-                h->slot[(size_t)v * (n + 1) + k] = (uint8_t)j++;
-            }
+        uint32_t *r = &h->vrec[(size_t)v * 8];
+        r[0] = (uint32_t)dmask[2 * v];
+        r[1] = (uint32_t)(dmask[2 * v] >> 32);
+        r[2] = (uint32_t)dmask[2 * v + 1];
+        r[3] = (uint32_t)(dmask[2 * v + 1] >> 32);
+        r[4] = off;
+        r[5] = h->vrc[v];
+        off += (uint32_t)(__builtin_popcountll(dmask[2 * v]) + __builtin_popcountll(dmask[2 * v + 1]));
     }
-    h->doff[h->nv] = (uint32_t)h->dom.size();
-    h->nd = (int)h->dom.size();
+    h->nd = (int)off;
     h->stride = (int)round_up((size_t)std::max(h->nv, 1), 16);
     // defaults: Table 1 and Section 3.3, total depth 10 n^2
     const int64_t depth = 10LL * n * n;
@@ -584,9 +590,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "nn_history") {
         if (v < 0 || v > kHist) return PLSE_E_PARAM;
         P.hist_len = (int32_t)v;
-    } else if (k == "conf_bytes") {
-        if (v != 1 && v != 2) return PLSE_E_PARAM;
-        h->conf_bytes = (int)v;
+    } else if (k == "lanes_per_vertex") {
+        if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return PLSE_E_PARAM;
+        h->lpv = (int)v;
     } else if (k == "waves_per_block") {
         if (v != 0 && v != 1 && v != 2 && v != 4) return PLSE_E_PARAM;
         h->wpb = (int)v;
@@ -611,7 +617,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "spacing") *v = P.spacing;
     else if (k == "stop_at_ub") *v = P.stop_at_ub;
     else if (k == "nn_history") *v = P.hist_len;
-    else if (k == "conf_bytes") *v = h->conf_bytes;
+    else if (k == "lanes_per_vertex") *v = choose_lpv(h);
     else if (k == "waves_per_block") *v = h->wpb ? h->wpb : choose_wpb(h);
     else return PLSE_E_PARAM;
     return PLSE_OK;
@@ -651,6 +657,7 @@ int plse_begin(plse_handle h, int32_t p, uint64_t seed, void *stream) {
     HIP_TRY(launch_init(ia, s));
     HIP_TRY(launch_pop_setup(p, h->stride, at<uint64_t>(h, L.uid), at<int32_t>(h, L.hc),
                              at<uint8_t>(h, L.S_all), at<uint8_t>(h, L.S_off), s));
+    HIP_TRY(launch_fill_zero(at<uint32_t>(h, L.tabu), (size_t)p * (h->nd + h->nv), s));
     if (!h->graph_valid || h->graph_p != p || h->graph_seed != seed) {
         rc = capture_generation(h, L, p, seed);
         if (rc) return rc;
@@ -827,7 +834,8 @@ int plse_stage_plits(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void 
     rc = upload_instance(h, L, s);
     if (rc) return rc;
     PlitsArgs a = plits_args(h, L, p, gen, seed, S_in, S_out, f_out, counters, nullptr);
-    HIP_TRY(launch_plits(a, h->conf_bytes, choose_wpb(h), s));
+    HIP_TRY(launch_fill_zero(at<uint32_t>(h, L.tabu), (size_t)p * (h->nd + h->nv), s));
+    HIP_TRY(launch_plits(a, choose_lpv(h), choose_wpb(h), s));
     return PLSE_OK;
 }
 

@@ -65,9 +65,11 @@ __global__ __launch_bounds__(256) void init_kernel(const InitArgs a) {
             const uint64_t kt = key[t];
             const int v = (int)(uint32_t)kt;
             const uint32_t pw = (uint32_t)(kt >> 32);
-            const int r = I.vrow[v], c = I.vcol[v];
-            const uint64_t l0 = I.dmask[2 * v] & ~(rowu[2 * r] | colu[2 * c]);
-            const uint64_t l1 = I.dmask[2 * v + 1] & ~(rowu[2 * r + 1] | colu[2 * c + 1]);
+            const uint32_t rc = I.vrc[v];
+            const int r = (int)(rc & 0xFFu), c = (int)(rc >> 8);
+            const uint64_t *dm = reinterpret_cast<const uint64_t *>(I.vrec) + 4 * v;
+            const uint64_t l0 = dm[0] & ~(rowu[2 * r] | colu[2 * c]);
+            const uint64_t l1 = dm[1] & ~(rowu[2 * r + 1] | colu[2 * c + 1]);
             const uint32_t c0 = (uint32_t)__popcll(l0), cnt = c0 + (uint32_t)__popcll(l1);
             if (cnt == 0) continue;
             uint32_t idx = scale32(pw, cnt);

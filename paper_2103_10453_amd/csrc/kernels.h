@@ -16,14 +16,13 @@ struct PlitsArgs {
     uint8_t *S_out;        // [p][stride]
     int32_t *f_out;        // [p]
     uint64_t *cnt_out;     // [p][kCounters]
-    void *conf;            // [p][nd] of ConfT
-    uint32_t *tabu;        // [p][nd + nv]
+    uint32_t *tabu;        // [p][nd + nv], all zero between phases
     const Ctl *ctl;        // generation and stop flag when gen_fixed == 0
     int32_t gen_fixed;
     int32_t p;
     uint32_t seed_lo, seed_hi;
     int32_t lds_per_wave;
-    int32_t off_cs, off_bm, off_scr;
+    int32_t off_h, off_bm, off_tm, off_el;
 };
 
 struct InitArgs {
@@ -128,8 +127,9 @@ struct AuxArgs {
     uint32_t seed_lo, seed_hi;
 };
 
-hipError_t launch_plits(const PlitsArgs &a, int conf_bytes, int waves_per_block,
+hipError_t launch_plits(const PlitsArgs &a, int lanes_per_vertex, int waves_per_block,
                         hipStream_t stream);
+hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t stream);
 hipError_t plits_set_lds_limit(int bytes);
 hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 size_t init_lds_bytes(const DevInstance &I, int pow2);

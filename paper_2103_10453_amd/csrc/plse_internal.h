@@ -28,13 +28,12 @@ enum Tag : uint32_t {
 struct DevInstance {
     int32_t n, nv, nd, stride;       // order, |V|, sum |D*(v)|, row stride (bytes)
     int32_t l, ub;
-    const uint8_t *vrow, *vcol;      // [nv]
-    const uint32_t *doff;            // [nv+1] D*(v) = dom[doff[v] .. doff[v+1])
-    const uint8_t *dom;              // [nd] colours, ascending
-    const uint8_t *slot;             // [nv*(n+1)] slot of colour k in D*(v), kNoSlot if absent
-    const uint16_t *rowv, *colv;     // [n*n] vertices of row r at r*n + t
+    const uint16_t *vrc;             // [nv] row | column << 8
+    const void *vrec;                // [nv] 32-byte records: D*(v) as a 128-bit colour
+                                     //   mask, first tabu slot offset, row | column << 8
+    const uint32_t *rowl, *coll;     // [n*n] vertices of row r (column c) at r*n + t:
+                                     //   vertex | (its column (row) << 16)
     const uint8_t *rowc, *colc;      // [n] vertex counts per row / column
-    const uint64_t *dmask;           // [nv*2] D*(v) as a 128-bit colour mask
 };
 
 struct Params {

@@ -59,20 +59,23 @@ def test_init_parity(torch_cuda, oracle_mod, name, p):
 
 
 # --- PLITS --------------------------------------------------------------------------
-@pytest.mark.parametrize("name,p,depth,conf_bytes,wpb", [
-    ("planted10", 64, 1000, 1, 0),
+@pytest.mark.parametrize("name,p,depth,lpv,wpb", [
+    ("planted10", 64, 1000, 0, 0),
+    ("planted10", 64, 1000, 8, 4),
     ("greedy12_60", 37, 1440, 1, 1),
     ("greedy12_60", 37, 1440, 2, 2),
-    ("greedy20_50", 65, 4000, 1, 4),
-    ("greedy20_50", 65, 4000, 2, 0),
-    ("planted33_45", 20, 10890, 1, 0),
-    ("greedy70_70", 9, 6000, 1, 0),
+    ("greedy20_50", 65, 4000, 4, 4),
+    ("greedy20_50", 65, 4000, 0, 0),
+    ("planted33_45", 20, 10890, 0, 0),
+    ("planted33_45", 20, 10890, 1, 1),
+    ("greedy70_70", 9, 6000, 0, 0),
+    ("greedy70_70", 9, 6000, 8, 2),
 ])
-def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, conf_bytes, wpb):
+def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, lpv, wpb):
     """S', f' and every per-individual counter equal the oracle's."""
     g = _instances()[name]
-    _say(f"plits {name} p={p} depth={depth} conf={conf_bytes} wpb={wpb}")
-    s = P.Solver(g, depth=depth, conf_bytes=conf_bytes, waves_per_block=wpb)
+    _say(f"plits {name} p={p} depth={depth} lpv={lpv} wpb={wpb}")
+    s = P.Solver(g, depth=depth, lanes_per_vertex=lpv, waves_per_block=wpb)
     seed, gen_no = 777 + p, 3
     S0, _ = s.stage_init(p, seed)
     S1, f1, c1 = s.stage_plits(S0, gen_no, seed)
@@ -114,7 +117,6 @@ def test_plits_from_conflicting_start(torch_cuda, oracle_mod):
         np.testing.assert_array_equal(_np(S1)[:, :I.nv], S1o)
         np.testing.assert_array_equal(_np(f1), f1o)
         np.testing.assert_array_equal(_np(c1).astype(np.uint64), c1o)
-    assert c1o[:, 7].sum() > 0 or True
 
 
 # --- distances, selection, matching, crossover --------------------------------------
@@ -180,9 +182,9 @@ def test_match_parity(torch_cuda, oracle_mod, p, seed):
     for i in range(p):
         k = int(rng.integers(0, 90))
         pool = np.concatenate([uid, (rng.integers(0, 10 * p, size=8) + (9 << 32)).astype(np.uint64)])
-        ex = rng.choice(pool, size=min(k, 64), replace=False)
+        ex = rng.choice(pool, size=min(k, 64, len(pool)), replace=False)
         hist[i, :len(ex)] = ex
-        hc[i] = k if k >= 64 else len(ex)
+        hc[i] = k if (k >= 64 and len(ex) == 64) else len(ex)
     import torch
     hist_t = torch.from_numpy(hist.view(np.int64)).cuda()
     hc_t = torch.from_numpy(hc).cuda()
@@ -246,9 +248,9 @@ def test_solve_repeatable_and_shape_independent(torch_cuda):
     g = gen.random_greedy(20, 0.5, 7)
     _say("solve repeat")
     outs = []
-    for conf_bytes, wpb in ((1, 0), (1, 1), (2, 2), (1, 4)):
-        s = P.Solver(g, depth=2000, conf_bytes=conf_bytes, waves_per_block=wpb)
-        for _ in range(2 if conf_bytes == 1 and wpb == 0 else 1):
+    for lpv, wpb in ((0, 0), (1, 1), (2, 2), (8, 4)):
+        s = P.Solver(g, depth=2000, lanes_per_vertex=lpv, waves_per_block=wpb)
+        for _ in range(2 if lpv == 0 and wpb == 0 else 1):
             grid, filled = s.solve(40, 3, 99)
             outs.append((grid.tobytes(), filled, s.stats()["totals"].tobytes()))
     assert len(set(outs)) == 1
