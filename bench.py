@@ -88,7 +88,20 @@ def main():
     ap.add_argument("--lanes-per-vertex", type=int, default=0)
     ap.add_argument("--population", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
+                    help="only run a plain elementwise device copy of MIB MiB (reads MIB, "
+                         "writes MIB), the reference for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.copy_reference:
+        import torch
+        n = args.copy_reference * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.add(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes_read": n * 4, "copy_reference_bytes_written": n * 4}))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
               "(see DESIGN.md for how the population would shard)", file=sys.stderr)

@@ -37,7 +37,7 @@ int colour_bits(int n) {
 
 // Offsets of every device array of one handle, for a population p.
 struct Layout {
-    size_t vrc, vrec, rowl, coll, rowc, colc;
+    size_t vrc, vrec, dom, rowl, coll, rowc, colc;
     size_t ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
     size_t tabu, planes, D, deg, adj, keys, rej, acc, hkeys, hvals, partner, dpart;
@@ -54,6 +54,7 @@ struct plse_instance {
     // host images of the device instance tables
     std::vector<uint16_t> vrc;
     std::vector<uint32_t> vrec;  // 8 words per vertex
+    std::vector<uint8_t> dom;    // domain colour lists
     std::vector<uint32_t> rowl, coll;
     std::vector<uint8_t> rowc, colc;
 
@@ -182,6 +183,7 @@ Layout plan(const plse_instance *h, int p) {
     const int W = (h->nv + 31) / 32, B = colour_bits(h->n);
     L.vrc = take(2 * nv);
     L.vrec = take(32 * nv);
+    L.dom = take(nd + 16);
     L.rowl = take(4 * n * n);
     L.coll = take(4 * n * n);
     L.rowc = take(n);
@@ -234,6 +236,7 @@ DevInstance dev_instance(plse_instance *h, const Layout &L) {
     I.ub = h->ub;
     I.vrc = at<uint16_t>(h, L.vrc);
     I.vrec = at<void>(h, L.vrec);
+    I.dom = at<uint8_t>(h, L.dom);
     I.rowl = at<uint32_t>(h, L.rowl);
     I.coll = at<uint32_t>(h, L.coll);
     I.rowc = at<uint8_t>(h, L.rowc);
@@ -248,6 +251,7 @@ int upload_instance(plse_instance *h, const Layout &L, hipStream_t s) {
     };
     HIP_TRY(put(L.vrc, h->vrc.data(), 2 * h->vrc.size()));
     HIP_TRY(put(L.vrec, h->vrec.data(), 4 * h->vrec.size()));
+    HIP_TRY(put(L.dom, h->dom.data(), h->dom.size()));
     HIP_TRY(put(L.rowl, h->rowl.data(), 4 * h->rowl.size()));
     HIP_TRY(put(L.coll, h->coll.data(), 4 * h->coll.size()));
     HIP_TRY(put(L.rowc, h->rowc.data(), h->rowc.size()));
@@ -509,9 +513,13 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
         r[1] = (uint32_t)(dmask[2 * v] >> 32);
         r[2] = (uint32_t)dmask[2 * v + 1];
         r[3] = (uint32_t)(dmask[2 * v + 1] >> 32);
+        const uint32_t d = (uint32_t)(__builtin_popcountll(dmask[2 * v]) +
+                                      __builtin_popcountll(dmask[2 * v + 1]));
         r[4] = off;
-        r[5] = h->vrc[v];
-        off += (uint32_t)(__builtin_popcountll(dmask[2 * v]) + __builtin_popcountll(dmask[2 * v + 1]));
+        r[5] = (uint32_t)h->vrc[v] | (d << 16);
+        for (int k = 1; k <= n; ++k)
+            if ((dmask[2 * v + (k >> 6)] >> (k & 63)) & 1ull) h->dom.push_back((uint8_t)k);
+        off += d;
     }
     h->nd = (int)off;
     h->stride = (int)round_up((size_t)std::max(h->nv, 1), 16);

@@ -20,9 +20,9 @@
 //
 // One iteration:
 //   1. eligible vertices V_0 u C(S) from the bitmap (wave prefix sum);
-//   2. LPV lanes per eligible vertex evaluate contiguous slices of its domain:
-//      move value from the row/column counts, admissibility from tabu and
-//      aspiration, best (value, tie-hash) key per lane;
+//   2. LPV lanes per eligible vertex evaluate interleaved slots of its domain,
+//      eight at a time: move value from the row/column counts, admissibility
+//      from tabu and aspiration, best (value, tie-hash) key per lane;
 //   3. DPP wave minimum picks the unique best admissible move;
 //   4. counts, colour, eligibility bits of the row/column vertices holding the
 //      old or new colour, tenure, tabu entry, best-solution snapshot.
@@ -47,11 +47,12 @@ struct Scal {
     int32_t fbest, cbest;
 };
 
-// 128-bit domain mask, first slot offset and coordinates of a vertex.
+// 128-bit domain mask, first slot offset, coordinates and domain size of a
+// vertex.
 struct VRec {
     uint64_t m0, m1;
     uint32_t doff;
-    int r, c;
+    int r, c, d;
 };
 
 __device__ __forceinline__ VRec load_rec(const DevInstance &I, int v) {
@@ -63,6 +64,7 @@ __device__ __forceinline__ VRec load_rec(const DevInstance &I, int v) {
     R.doff = b.x;
     R.r = (int)(b.y & 0xFFu);
     R.c = (int)((b.y >> 8) & 0xFFu);
+    R.d = (int)(b.y >> 16);
     return R;
 }
 
@@ -131,9 +133,8 @@ __device__ void clear_tabu(const DevInstance &I, uint32_t *tabu, const WaveState
     for (int v = lane_id(); v < I.nv; v += 64) {
         if (ws.tmax[v]) {
             const VRec R = load_rec(I, v);
-            const int d = __popcll(R.m0) + __popcll(R.m1);
             uint32_t *tb = tabu + R.doff + v;
-            for (int t = 0; t <= d; ++t) tb[t] = 0u;
+            for (int t = 0; t <= R.d; ++t) tb[t] = 0u;
         }
     }
 }
@@ -185,7 +186,13 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         const U4 rw = draw(a.seed_lo, a.seed_hi, slot, gen, tag, (uint32_t)it);
         const uint32_t itu = (uint32_t)it;
 
-        // 2. best admissible one-move per lane
+        // 2. best admissible one-move per lane.  Lane q of a vertex's group
+        //    takes domain slots q, q + LPV, ...; eight slots per batch: the
+        //    colour and tabu loads of a batch are issued together, then its
+        //    row/column count reads, then branch-free key selection.
+        //    Aspiration F + delta < F* is delta < thr (F* - F clamped to int32).
+        const int64_t gap = sc.Fbest - sc.F;
+        const int32_t thr = gap < (int64_t)INT32_MIN ? INT32_MIN : (int32_t)gap;
         uint64_t lbest = ~0ull;
         uint32_t lpay = 0u;
         for (uint32_t e = (uint32_t)grp; e < m; e += VPP) {
@@ -197,60 +204,44 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             const int32_t cur = s ? ((int32_t)rH[s] + (int32_t)cH[s] - 2) : 0;
             const bool live = ws.tmax[v] > itu;
             const uint32_t *tb = tabu + R.doff + v;  // [0] colour 0, [1 + j] slot j
-            const int d = __popcll(R.m0) + __popcll(R.m1);
+            const uint8_t *dl = I.dom + R.doff;      // colours of D*(v), ascending
+            const int d = R.d;
             if (q == 0) lane_cands += (uint32_t)d;
             const int32_t dfb = s ? 0 : -phi_den;
             const uint32_t cid0 = (uint32_t)(v * np1);
-            // contiguous slice of slots for this lane
-            const int chunk = (d + LPV - 1) / LPV;
-            const int j0 = q * chunk, j1 = min(d, j0 + chunk);
-            uint64_t m0 = R.m0, m1 = R.m1;
-            for (int t = 0; t < j0; ++t) {
-                if (m0) m0 &= m0 - 1ull;
-                else m1 &= m1 - 1ull;
-            }
-            for (int jb = j0; jb < j1; jb += 8) {
+            for (int jb = q; jb < d; jb += 8 * LPV) {
+                int kk[8];
                 uint32_t tv[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) tv[t] = (live && jb + t < j1) ? tb[1 + jb + t] : 0u;
+                for (int t = 0; t < 8; ++t) {
+                    const int j = jb + t * LPV;
+                    kk[t] = (j < d) ? (int)dl[j] : 0;
+                    tv[t] = (live && j < d) ? tb[1 + j] : 0u;
+                }
+                int cnt[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) cnt[t] = (int)rH[kk[t]] + (int)cH[kk[t]];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                    if (jb + t < j1) {
-                        int k;
-                        if (m0) {
-                            k = __ffsll((unsigned long long)m0) - 1;
-                            m0 &= m0 - 1ull;
-                        } else {
-                            k = 64 + __ffsll((unsigned long long)m1) - 1;
-                            m1 &= m1 - 1ull;
-                        }
-                        if (k != s) {
-                            const int32_t delta =
-                                dfb + phi_num * ((int32_t)rH[k] + (int32_t)cH[k] - cur);
-                            if (itu >= tv[t] || sc.F + delta < sc.Fbest) {
-                                const uint64_t key =
-                                    ((uint64_t)((uint32_t)delta + 0x80000000u) << 32) |
-                                    fmix32(rw.y ^ (cid0 + (uint32_t)k));
-                                if (key < lbest) {
-                                    lbest = key;
-                                    lpay = ((uint32_t)v << 8) | (uint32_t)k;
-                                }
-                            }
-                        }
-                    }
+                    const int j = jb + t * LPV;
+                    const int k = kk[t];
+                    const int32_t delta = dfb + phi_num * (cnt[t] - cur);
+                    const bool ok = (j < d) && (k != s) && (itu >= tv[t] || delta < thr);
+                    const uint64_t key = ((uint64_t)((uint32_t)delta + 0x80000000u) << 32) |
+                                         fmix32(rw.y ^ (cid0 + (uint32_t)k));
+                    const bool take = ok && key < lbest;
+                    lbest = take ? key : lbest;
+                    lpay = take ? (((uint32_t)v << 8) | (uint32_t)k) : lpay;
                 }
             }
             if (s && q == 0) {  // a conflicting vertex may also become uncoloured
                 const int32_t delta = phi_den - phi_num * cur;
                 const uint32_t t0 = live ? tb[0] : 0u;
-                if (itu >= t0 || sc.F + delta < sc.Fbest) {
-                    const uint64_t key =
-                        ((uint64_t)((uint32_t)delta + 0x80000000u) << 32) | fmix32(rw.y ^ cid0);
-                    if (key < lbest) {
-                        lbest = key;
-                        lpay = (uint32_t)v << 8;
-                    }
-                }
+                const uint64_t key =
+                    ((uint64_t)((uint32_t)delta + 0x80000000u) << 32) | fmix32(rw.y ^ cid0);
+                const bool take = (itu >= t0 || delta < thr) && key < lbest;
+                lbest = take ? key : lbest;
+                lpay = take ? ((uint32_t)v << 8) : lpay;
             }
         }
         // 3. unique best over the wave

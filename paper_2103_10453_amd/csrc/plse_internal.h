@@ -30,7 +30,9 @@ struct DevInstance {
     int32_t l, ub;
     const uint16_t *vrc;             // [nv] row | column << 8
     const void *vrec;                // [nv] 32-byte records: D*(v) as a 128-bit colour
-                                     //   mask, first tabu slot offset, row | column << 8
+                                     //   mask, first slot offset, row | column << 8 |
+                                     //   |D*(v)| << 16
+    const uint8_t *dom;              // [nd] colours of D*(v) at [first slot offset ..)
     const uint32_t *rowl, *coll;     // [n*n] vertices of row r (column c) at r*n + t:
                                      //   vertex | (its column (row) << 16)
     const uint8_t *rowc, *colc;      // [n] vertex counts per row / column
