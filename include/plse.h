@@ -29,7 +29,8 @@ enum {
     PLSE_E_BUSY = 5,       /* the handle is already running a call              */
     PLSE_PENDING = 6,      /* server: request not finished yet                  */
     PLSE_E_PARAM = 7,      /* unknown parameter key or value out of range       */
-    PLSE_E_CAPACITY = 8    /* server: request cannot ever fit the budget        */
+    PLSE_E_CAPACITY = 8,   /* server: request cannot ever fit the budget        */
+    PLSE_E_FAULT = 9       /* server: request ended by the fault-injection hook */
 };
 
 typedef struct plse_instance *plse_handle;
@@ -98,6 +99,8 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *                 LDS footprint)
  * Errors: PLSE_E_PARAM.
  */
+/* Test hook (serving): "fail_at_generation" g > 0 makes a served request end
+ * with PLSE_E_FAULT after its generation g, without touching other requests. */
 int plse_set_param(plse_handle h, const char *key, int64_t value);
 int plse_get_param(plse_handle h, const char *key, int64_t *value);
 
@@ -148,6 +151,25 @@ int plse_solve(plse_handle h, int32_t population, int32_t generations, uint64_t 
 int plse_begin(plse_handle h, int32_t population, uint64_t seed, void *stream);
 int plse_step(plse_handle h, int32_t generations, void *stream);
 int plse_end(plse_handle h, void *stream, int8_t *best_grid, int32_t *filled);
+
+/*
+ * plse_solve_batch -- plse_solve on `count` instances at once.
+ *
+ * Every generation of Alg. 2 runs for all instances together: one launch per
+ * kernel covers the instances (grouped by PLITS launch shape and by colour
+ * width, longest estimated work first), captured once as HIP graphs and
+ * replayed per generation.  Each handle needs its own attached workspace of
+ * plse_workspace_bytes(hs[i], population); the handles must be distinct and
+ * idle.  seeds[i], best_grids[i] (host n_i*n_i) and filled[i] belong to
+ * hs[i].  The result of each instance is identical to plse_solve of that
+ * instance alone with the same arguments.  Per-instance statistics and
+ * timings are then available through plse_last_stats / plse_last_timing.
+ * Errors: PLSE_E_ARG (null, duplicate handle, bad sizes), PLSE_E_WORKSPACE,
+ * PLSE_E_BUSY, PLSE_E_HIP.
+ */
+int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t population,
+                     int32_t generations, const uint64_t *seeds, void *stream,
+                     int8_t *const *best_grids, int32_t *filled);
 
 /* Per-generation GPU times of the last session, from the HIP events of
  * plse_step: plits_ms[g] spans the tabu-search launch of generation g,
@@ -208,6 +230,55 @@ int plse_stage_match(plse_handle h, int32_t population, void *stream, const int1
 int plse_stage_aux(plse_handle h, int32_t population, int32_t gen, uint64_t seed, void *stream,
                    const uint8_t *S, const int32_t *partner, const int32_t *dpart,
                    uint8_t *S_off);
+
+/*
+ * Serving: continuous batching of solve requests on one device.
+ *
+ * A server owns a device arena (caller memory, hbm_budget_bytes) and a worker
+ * thread.  Requests wait in arrival order; at every generation boundary the
+ * worker retires finished requests and admits waiting ones while their
+ * workspace (plse_workspace_bytes) fits in the free arena and fewer than
+ * max_slots are resident.  Each step runs one generation of Alg. 2 for every
+ * resident request in batched launches (as plse_solve_batch), so requests
+ * that arrive while others run share the device with them.  Each result is
+ * identical to plse_solve of the same instance, parameters, population,
+ * generations and seed, whatever else is resident.
+ *
+ * plse_server_create: device_ptr/hbm_budget_bytes the arena (256-byte
+ *   aligned, caller-owned, must outlive the server); max_slots >= 1; stream
+ *   the HIP stream the worker uses.
+ * plse_server_submit: the handle is used by the server until its result has
+ *   been polled (do not touch it meanwhile).  Returns PLSE_E_CAPACITY if the
+ *   request's workspace can never fit the arena; *ticket identifies it.
+ * plse_server_poll: PLSE_PENDING while the request runs; then fills the grid
+ *   (host n*n), filled and the timing record, returns the request's own status
+ *   (PLSE_OK, or the error that ended it) and forgets the ticket.
+ * plse_server_destroy: stops the worker after the resident requests finish
+ *   their current generation; waiting and resident requests are dropped.
+ */
+typedef struct plse_server_s *plse_server;
+
+typedef struct {
+    double submit_s;        /* seconds since the server was created          */
+    double admit_s;         /* admitted (workspace placed, population built) */
+    double done_s;          /* last generation finished                      */
+    double best_s;          /* end of the generation that found S*           */
+    int32_t generations;    /* generations run                               */
+    int32_t best_generation;
+    int32_t filled;
+    int32_t status;
+    uint64_t moves;         /* tabu moves executed for this request          */
+} plse_timing;
+
+int plse_server_create(size_t hbm_budget_bytes, void *device_ptr, int32_t max_slots, void *stream,
+                       plse_server *out);
+int plse_server_submit(plse_server s, plse_handle h, int32_t population, int32_t generations,
+                       uint64_t seed, uint64_t *ticket);
+int plse_server_poll(plse_server s, uint64_t ticket, int8_t *best_grid, int32_t *filled,
+                     plse_timing *timing);
+/* Requests waiting, resident, and finished but not yet polled. */
+int plse_server_status(plse_server s, int32_t *waiting, int32_t *resident, int32_t *finished);
+int plse_server_destroy(plse_server s);
 
 #ifdef __cplusplus
 }

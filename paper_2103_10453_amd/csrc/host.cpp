@@ -1,14 +1,20 @@
 // host.cpp -- libplse host side: instance preprocessing (Section 2.2, Alg. 1),
-// workspace planning, the per-generation HIP graph (Alg. 2) and the C ABI of
-// include/plse.h.
+// workspace planning, sessions of one or many instances driving the
+// per-generation HIP graphs (Alg. 2), and the C ABI of include/plse.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <climits>
+#include <condition_variable>
+#include <cstddef>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/plse.h"
@@ -38,12 +44,32 @@ int colour_bits(int n) {
 // Offsets of every device array of one handle, for a population p.
 struct Layout {
     size_t vrc, vrec, dom, rowl, coll, rowc, colc;
-    size_t ctl, stats, Sstar;
+    size_t args, ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
     size_t tabu, planes, D, deg, adj, keys, rej, acc, hkeys, hvals, partner, dpart;
     size_t total;
     int pow2_sel, hsize;
 };
+
+// Argument blocks of every kernel of one instance; a device copy lives in
+// the instance's workspace and launches pass its address.
+struct ArgBlock {
+    PlitsArgs plits;
+    InitArgs init;
+    BestArgs best;
+    PackArgs pack;
+    DistArgs dist;
+    CloseArgs close;
+    SelectArgs select;
+    GatherArgs gather;
+    HashArgs hash;
+    MatchArgs match;
+    AuxArgs aux;
+    PopSetupArgs pop;
+    FillArgs fill;
+};
+
+struct Session;
 
 }  // namespace
 
@@ -61,28 +87,20 @@ struct plse_instance {
     Params P{};
     int lpv = 0;  // lanes per eligible vertex in PLITS; 0: automatic
     int wpb = 0;  // waves per block in PLITS; 0: automatic
+    int fail_at = 0;  // serving test hook: end the request after this generation
 
     uint8_t *ws = nullptr;
     size_t ws_bytes = 0;
+    Layout L{};
+    ArgBlock args{};
 
-    // generation graphs: [gen_begin, plits] and [best .. aux]; HIP events
-    // around the first measure the tabu-search kernel on the caller's stream
-    hipGraphExec_t exec_ls = nullptr, exec_rest = nullptr;
-    bool graph_valid = false;
-    int graph_p = 0;
-    uint64_t graph_seed = 0;
-
-    // session (plse_begin / plse_step / plse_end)
+    Session *own = nullptr;  // session of plse_begin / plse_step / plse_end
     bool in_session = false;
-    int sess_p = 0;
-    uint64_t sess_seed = 0;
-    int sess_steps = 0;
-    std::vector<hipEvent_t> ev;  // 3 per generation: before plits, after, end of generation
-    std::vector<float> ms_plits, ms_rest;
 
     plse_stats last{};
     std::vector<int32_t> gen_best;
     std::vector<uint64_t> gen_cnt;
+    std::vector<float> ms_plits, ms_rest;
     std::atomic<int> busy{0};
 };
 
@@ -102,8 +120,14 @@ int hip_fail(hipError_t e, const char *what = nullptr) {
         if (e_ != hipSuccess) return hip_fail(e_, #x);  \
     } while (0)
 
+#define RC_TRY(x)            \
+    do {                     \
+        const int rc_ = (x); \
+        if (rc_) return rc_; \
+    } while (0)
+
 std::once_flag g_attr_once;
-int g_lds_limit = 65536;  // dynamic LDS per block every kernel may use
+int g_lds_limit = 65536 - 1024;  // dynamic LDS per block every kernel may use
 
 // Raise the dynamic-LDS limit of the kernels to the device's per-block LDS.
 // If the runtime refuses, kernels keep the default 64 KiB and launch shapes
@@ -144,20 +168,22 @@ PlitsLds plits_lds(const plse_instance *h) {
 }
 
 // Waves per block maximising resident waves per CU under the LDS budget.
-int choose_wpb(const plse_instance *h) {
-    if (h->wpb) return h->wpb;
-    const int per = plits_lds(h).per_wave;
+int auto_wpb(int per_wave) {
     const int lim = max_lds_per_block();
     int best = 1, best_waves = 0;
     for (int w : {1, 2, 4}) {
-        if (w * per > lim) continue;
-        const int waves = (lim / (w * per)) * w;
+        if (w * per_wave > lim) continue;
+        const int waves = (lim / (w * per_wave)) * w;
         if (waves >= best_waves) {
             best = w;
             best_waves = waves;
         }
     }
     return best;
+}
+
+int choose_wpb(const plse_instance *h) {
+    return h->wpb ? h->wpb : auto_wpb(plits_lds(h).per_wave);
 }
 
 // Lanes per eligible vertex: about four domain colours per lane.
@@ -188,6 +214,7 @@ Layout plan(const plse_instance *h, int p) {
     L.coll = take(4 * n * n);
     L.rowc = take(n);
     L.colc = take(n);
+    L.args = take(sizeof(ArgBlock));
     L.ctl = take(sizeof(Ctl));
     L.stats = take(sizeof(GenStat) * PLSE_MAX_GENERATIONS);
     L.Sstar = take(st);
@@ -226,7 +253,8 @@ T *at(plse_instance *h, size_t off) {
     return reinterpret_cast<T *>(h->ws + off);
 }
 
-DevInstance dev_instance(plse_instance *h, const Layout &L) {
+DevInstance dev_instance(plse_instance *h) {
+    const Layout &L = h->L;
     DevInstance I;
     I.n = h->n;
     I.nv = h->nv;
@@ -244,7 +272,8 @@ DevInstance dev_instance(plse_instance *h, const Layout &L) {
     return I;
 }
 
-int upload_instance(plse_instance *h, const Layout &L, hipStream_t s) {
+int upload_instance(plse_instance *h, hipStream_t s) {
+    const Layout &L = h->L;
     auto put = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(h->ws + off, src, bytes, hipMemcpyHostToDevice, s);
@@ -259,17 +288,31 @@ int upload_instance(plse_instance *h, const Layout &L, hipStream_t s) {
     return PLSE_OK;
 }
 
-PlitsArgs plits_args(plse_instance *h, const Layout &L, int p, int gen_fixed, uint64_t seed,
+int upload_args(plse_instance *h, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(h->ws + h->L.args, &h->args, sizeof(ArgBlock), hipMemcpyHostToDevice,
+                           s));
+    return PLSE_OK;
+}
+
+// Device address of one argument block of h.
+template <typename M>
+const void *dev_arg(plse_instance *h, M ArgBlock::*member) {
+    const size_t off = (size_t)(reinterpret_cast<const char *>(&(h->args.*member)) -
+                                reinterpret_cast<const char *>(&h->args));
+    return h->ws + h->L.args + off;
+}
+
+PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
                      const uint8_t *S_in, uint8_t *S_out, int32_t *f_out, uint64_t *cnt,
                      const Ctl *ctl) {
     PlitsArgs a{};
-    a.I = dev_instance(h, L);
+    a.I = dev_instance(h);
     a.P = h->P;
     a.S_in = S_in;
     a.S_out = S_out;
     a.f_out = f_out;
     a.cnt_out = cnt;
-    a.tabu = at<uint32_t>(h, L.tabu);
+    a.tabu = at<uint32_t>(h, h->L.tabu);
     a.ctl = ctl;
     a.gen_fixed = gen_fixed;
     a.p = p;
@@ -284,98 +327,166 @@ PlitsArgs plits_args(plse_instance *h, const Layout &L, int p, int gen_fixed, ui
     return a;
 }
 
-int launch_select_stage(plse_instance *h, const Layout &L, int p, int gen_fixed, uint64_t seed,
-                        const Ctl *ctl, const int32_t *f_all, const int16_t *D, int ld,
-                        int32_t *acc, hipStream_t s) {
-    const int m = 2 * p;
-    CloseArgs ca{ctl, D, at<int32_t>(h, L.deg), at<uint16_t>(h, L.adj), m, ld, h->nv,
-                 h->P.spacing};
-    HIP_TRY(launch_close(ca, s));
-    SelectArgs sa{};
-    sa.ctl = ctl;
-    sa.f_all = f_all;
-    sa.D = D;
-    sa.deg = at<int32_t>(h, L.deg);
-    sa.adj = at<uint16_t>(h, L.adj);
-    sa.keys_g = at<uint64_t>(h, L.keys);
-    sa.rej = at<int32_t>(h, L.rej);
-    sa.acc = acc;
-    sa.p = p;
-    sa.m = m;
-    sa.ld = ld;
-    sa.nv = h->nv;
-    sa.pow2 = L.pow2_sel;
-    sa.keys_in_lds =
-        select_lds_bytes(m, L.pow2_sel, true) <= (size_t)max_lds_per_block() ? 1 : 0;
-    sa.gen_fixed = gen_fixed;
-    sa.spacing = h->P.spacing;
-    sa.seed_lo = (uint32_t)seed;
-    sa.seed_hi = (uint32_t)(seed >> 32);
-    HIP_TRY(launch_select(sa, s));
-    return PLSE_OK;
+SelectArgs make_select(plse_instance *h, int p, int gen_fixed, uint64_t seed, const Ctl *ctl,
+                       const int32_t *f_all, const int16_t *D, int ld, int32_t *acc) {
+    const Layout &L = h->L;
+    SelectArgs a{};
+    a.ctl = ctl;
+    a.f_all = f_all;
+    a.D = D;
+    a.deg = at<int32_t>(h, L.deg);
+    a.adj = at<uint16_t>(h, L.adj);
+    a.keys_g = at<uint64_t>(h, L.keys);
+    a.rej = at<int32_t>(h, L.rej);
+    a.acc = acc;
+    a.p = p;
+    a.m = 2 * p;
+    a.ld = ld;
+    a.nv = h->nv;
+    a.pow2 = L.pow2_sel;
+    a.keys_in_lds =
+        select_lds_bytes(2 * p, L.pow2_sel, true) <= (size_t)max_lds_per_block() ? 1 : 0;
+    a.gen_fixed = gen_fixed;
+    a.spacing = h->P.spacing;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    return a;
 }
 
-int launch_match_stage(plse_instance *h, const Layout &L, int p, const Ctl *ctl,
-                       const int16_t *D, int ld, const int32_t *idx, const uint64_t *uid,
-                       uint64_t *hist, int32_t *hc, int32_t *partner, int32_t *dpart,
-                       hipStream_t s) {
-    HashArgs ha{ctl, uid, at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals), p, L.hsize};
-    MatchArgs ma{ctl, D, idx, uid, hist, hc, at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals),
-                 partner, dpart, p, ld, L.hsize, h->P.hist_len};
-    HIP_TRY(launch_match(ha, ma, s));
-    return PLSE_OK;
+size_t select_lds(plse_instance *h, int p) {
+    return select_lds_bytes(2 * p, h->L.pow2_sel, h->args.select.keys_in_lds != 0);
 }
 
-// One generation of Alg. 2 on the device; every kernel reads the generation
-// number and the stop flag from the control block.
-int enqueue_local_search(plse_instance *h, const Layout &L, int p, uint64_t seed,
-                         hipStream_t s) {
-    Ctl *ctl = at<Ctl>(h, L.ctl);
-    const int st = h->stride;
-    uint8_t *S_new = at<uint8_t>(h, L.S_all) + (size_t)p * st;
-    int32_t *f_all = at<int32_t>(h, L.f_all);
-    HIP_TRY(launch_gen_begin(ctl, s));
-    PlitsArgs pa = plits_args(h, L, p, 0, seed, at<uint8_t>(h, L.S_off), S_new, f_all + p,
-                              at<uint64_t>(h, L.cnt), ctl);
-    HIP_TRY(launch_plits(pa, choose_lpv(h), choose_wpb(h), s));
-    return PLSE_OK;
-}
-
-int enqueue_rest(plse_instance *h, const Layout &L, int p, uint64_t seed, hipStream_t s) {
-    Ctl *ctl = at<Ctl>(h, L.ctl);
+// Argument blocks of the whole pipeline of a solve with population p.
+void build_pipeline_args(plse_instance *h, int p, uint64_t seed) {
+    const Layout &L = h->L;
+    ArgBlock &A = h->args;
     const int st = h->stride, m = 2 * p;
+    Ctl *ctl = at<Ctl>(h, L.ctl);
     uint8_t *S_all = at<uint8_t>(h, L.S_all);
     uint8_t *S_new = S_all + (size_t)p * st;
     int32_t *f_all = at<int32_t>(h, L.f_all);
-    BestArgs ba{ctl, at<GenStat>(h, L.stats), f_all + p, S_new, at<uint64_t>(h, L.cnt),
-                at<uint8_t>(h, L.Sstar), p, st, h->n * h->n - h->l, h->ub, h->P.stop_at_ub};
-    HIP_TRY(launch_best(ba, s));
-    HIP_TRY(launch_distances(ctl, S_all, at<uint32_t>(h, L.planes), at<int16_t>(h, L.D), m,
-                             h->nv, st, m, colour_bits(h->n), s));
-    int rc = launch_select_stage(h, L, p, 0, seed, ctl, f_all, at<int16_t>(h, L.D), m,
-                                 at<int32_t>(h, L.acc), s);
-    if (rc) return rc;
-    GatherArgs ga{ctl, at<int32_t>(h, L.acc), S_all, f_all, at<uint64_t>(h, L.uid),
-                  at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc), at<uint8_t>(h, L.S_tmp),
-                  at<int32_t>(h, L.f_tmp), at<uint64_t>(h, L.uid_tmp),
-                  at<uint64_t>(h, L.hist_tmp), at<int32_t>(h, L.hc_tmp), p, st};
-    HIP_TRY(launch_gather(ga, s));
-    rc = launch_match_stage(h, L, p, ctl, at<int16_t>(h, L.D), m, at<int32_t>(h, L.acc),
-                            at<uint64_t>(h, L.uid), at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc),
-                            at<int32_t>(h, L.partner), at<int32_t>(h, L.dpart), s);
-    if (rc) return rc;
-    AuxArgs xa{ctl, S_all, at<int32_t>(h, L.partner), at<int32_t>(h, L.dpart),
-               at<uint8_t>(h, L.S_off), p, h->nv, st, 0, h->P.beta_num, h->P.beta_den,
-               (uint32_t)seed, (uint32_t)(seed >> 32)};
-    HIP_TRY(launch_aux(xa, s));
+    const uint32_t slo = (uint32_t)seed, shi = (uint32_t)(seed >> 32);
+    A.init = InitArgs{dev_instance(h), S_all, f_all, p, next_pow2(std::max(4, h->nv)), slo, shi};
+    A.pop = PopSetupArgs{p, st, at<uint64_t>(h, L.uid), at<int32_t>(h, L.hc), S_all,
+                         at<uint8_t>(h, L.S_off)};
+    A.fill = FillArgs{at<uint32_t>(h, L.tabu), (size_t)p * (h->nd + h->nv)};
+    A.plits = make_plits(h, p, 0, seed, at<uint8_t>(h, L.S_off), S_new, f_all + p,
+                         at<uint64_t>(h, L.cnt), ctl);
+    A.best = BestArgs{ctl, at<GenStat>(h, L.stats), f_all + p, S_new, at<uint64_t>(h, L.cnt),
+                      at<uint8_t>(h, L.Sstar), p, st, h->n * h->n - h->l, h->ub,
+                      h->P.stop_at_ub};
+    const int W = (h->nv + 31) / 32;
+    A.pack = PackArgs{ctl, S_all, at<uint32_t>(h, L.planes), m, h->nv, st, W, colour_bits(h->n)};
+    const int nt1 = (m + 63) / 64;
+    A.dist = DistArgs{ctl, at<uint32_t>(h, L.planes), at<int16_t>(h, L.D), m, W, m, nt1};
+    A.close = CloseArgs{ctl, at<int16_t>(h, L.D), at<int32_t>(h, L.deg), at<uint16_t>(h, L.adj),
+                        m, m, h->nv, h->P.spacing};
+    A.select = make_select(h, p, 0, seed, ctl, f_all, at<int16_t>(h, L.D), m,
+                           at<int32_t>(h, L.acc));
+    A.gather = GatherArgs{ctl, at<int32_t>(h, L.acc), S_all, f_all, at<uint64_t>(h, L.uid),
+                          at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc), at<uint8_t>(h, L.S_tmp),
+                          at<int32_t>(h, L.f_tmp), at<uint64_t>(h, L.uid_tmp),
+                          at<uint64_t>(h, L.hist_tmp), at<int32_t>(h, L.hc_tmp), p, st};
+    A.hash = HashArgs{ctl, at<uint64_t>(h, L.uid), at<uint64_t>(h, L.hkeys),
+                      at<int32_t>(h, L.hvals), p, L.hsize};
+    A.match = MatchArgs{ctl, at<int16_t>(h, L.D), at<int32_t>(h, L.acc), at<uint64_t>(h, L.uid),
+                        at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc), at<uint64_t>(h, L.hkeys),
+                        at<int32_t>(h, L.hvals), at<int32_t>(h, L.partner),
+                        at<int32_t>(h, L.dpart), p, m, L.hsize, h->P.hist_len};
+    A.aux = AuxArgs{ctl, S_all, at<int32_t>(h, L.partner), at<int32_t>(h, L.dpart),
+                    at<uint8_t>(h, L.S_off), p, h->nv, st, 0, h->P.beta_num, h->P.beta_den, slo,
+                    shi};
+}
+
+// Launch `fn` over the instances `hs`, kMaxLaunch at a time.
+template <typename M, typename F>
+int launch_over(const std::vector<plse_instance *> &hs, M ArgBlock::*member, F &&fn) {
+    for (size_t b = 0; b < hs.size(); b += kMaxLaunch) {
+        ArgList L{};
+        const int count = (int)std::min<size_t>(kMaxLaunch, hs.size() - b);
+        for (int i = 0; i < count; ++i) L.p[i] = dev_arg(hs[b + i], member);
+        HIP_TRY(fn(L, count));
+    }
     return PLSE_OK;
 }
 
-void drop_graph(plse_instance *h) {
-    if (h->exec_ls) (void)hipGraphExecDestroy(h->exec_ls);
-    if (h->exec_rest) (void)hipGraphExecDestroy(h->exec_rest);
-    h->exec_ls = h->exec_rest = nullptr;
-    h->graph_valid = false;
+int launch_ctl(const std::vector<plse_instance *> &hs, bool reset, hipStream_t s) {
+    for (size_t b = 0; b < hs.size(); b += kMaxLaunch) {
+        ArgList L{};
+        const int count = (int)std::min<size_t>(kMaxLaunch, hs.size() - b);
+        for (int i = 0; i < count; ++i) L.p[i] = at<Ctl>(hs[b + i], hs[b + i]->L.ctl);
+        if (reset)
+            HIP_TRY(launch_ctl_reset(L, count, s));
+        else
+            HIP_TRY(launch_gen_begin(L, count, s));
+    }
+    return PLSE_OK;
+}
+
+// A solve over one or many instances sharing the population size.
+struct Session {
+    std::vector<plse_instance *> hs;  // launch order: longest estimated work first
+    int p = 0;
+    int steps = 0;
+    int wpb = 1, lds_per_wave = 0;
+    hipGraphExec_t ls = nullptr, rest = nullptr;
+    std::vector<hipEvent_t> ev;  // 3 per generation
+
+    ~Session() {
+        if (ls) (void)hipGraphExecDestroy(ls);
+        if (rest) (void)hipGraphExecDestroy(rest);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+int enqueue_local_search(Session &S, hipStream_t s) {
+    RC_TRY(launch_ctl(S.hs, false, s));
+    for (int lpv : {1, 2, 4, 8}) {
+        std::vector<plse_instance *> g;
+        for (plse_instance *h : S.hs)
+            if (choose_lpv(h) == lpv) g.push_back(h);
+        if (g.empty()) continue;
+        RC_TRY(launch_over(g, &ArgBlock::plits, [&](const ArgList &L, int c) {
+            return launch_plits(L, c, S.p, S.lds_per_wave, lpv, S.wpb, s);
+        }));
+    }
+    return PLSE_OK;
+}
+
+int enqueue_rest(Session &S, hipStream_t s) {
+    const int p = S.p, m = 2 * p;
+    RC_TRY(launch_over(S.hs, &ArgBlock::best,
+                       [&](const ArgList &L, int c) { return launch_best(L, c, s); }));
+    size_t pack_threads = 0;
+    for (plse_instance *h : S.hs)
+        pack_threads = std::max(pack_threads, (size_t)m * ((h->nv + 31) / 32));
+    RC_TRY(launch_over(S.hs, &ArgBlock::pack, [&](const ArgList &L, int c) {
+        return launch_pack(L, c, pack_threads, s);
+    }));
+    for (int B = 1; B <= 7; ++B) {
+        std::vector<plse_instance *> g;
+        for (plse_instance *h : S.hs)
+            if (colour_bits(h->n) == B) g.push_back(h);
+        if (g.empty()) continue;
+        RC_TRY(launch_over(g, &ArgBlock::dist,
+                           [&](const ArgList &L, int c) { return launch_dist(L, c, m, B, s); }));
+    }
+    RC_TRY(launch_over(S.hs, &ArgBlock::close,
+                       [&](const ArgList &L, int c) { return launch_close(L, c, m, s); }));
+    const size_t sl = select_lds(S.hs[0], p);
+    RC_TRY(launch_over(S.hs, &ArgBlock::select,
+                       [&](const ArgList &L, int c) { return launch_select(L, c, sl, s); }));
+    RC_TRY(launch_over(S.hs, &ArgBlock::gather,
+                       [&](const ArgList &L, int c) { return launch_gather(L, c, p, s); }));
+    const int hsize = S.hs[0]->L.hsize;
+    RC_TRY(launch_over(S.hs, &ArgBlock::hash,
+                       [&](const ArgList &L, int c) { return launch_hash(L, c, p, hsize, s); }));
+    RC_TRY(launch_over(S.hs, &ArgBlock::match,
+                       [&](const ArgList &L, int c) { return launch_match(L, c, p, s); }));
+    RC_TRY(launch_over(S.hs, &ArgBlock::aux,
+                       [&](const ArgList &L, int c) { return launch_aux(L, c, p, s); }));
+    return PLSE_OK;
 }
 
 template <typename F>
@@ -385,7 +496,7 @@ int capture(F &&enqueue, hipGraphExec_t *out) {
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) {
         (void)hipStreamDestroy(cs);
-        return hip_fail(e);
+        return hip_fail(e, "hipStreamBeginCapture");
     }
     const int rc = enqueue(cs);
     hipGraph_t g = nullptr;
@@ -395,37 +506,151 @@ int capture(F &&enqueue, hipGraphExec_t *out) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
     }
-    if (e != hipSuccess) return hip_fail(e);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         *out = nullptr;
-        return hip_fail(e);
+        return hip_fail(e, "hipGraphInstantiate");
     }
     return PLSE_OK;
 }
 
-int capture_generation(plse_instance *h, const Layout &L, int p, uint64_t seed) {
-    drop_graph(h);
-    int rc = capture([&](hipStream_t cs) { return enqueue_local_search(h, L, p, seed, cs); },
-                     &h->exec_ls);
-    if (rc) return rc;
-    rc = capture([&](hipStream_t cs) { return enqueue_rest(h, L, p, seed, cs); }, &h->exec_rest);
-    if (rc) {
-        drop_graph(h);
-        return rc;
-    }
-    h->graph_valid = true;
-    h->graph_p = p;
-    h->graph_seed = seed;
+// Estimated work per generation of one individual: depth x mean domain size.
+double work_estimate(const plse_instance *h) {
+    return (double)(h->P.depth1 + h->P.depth2) * (1.0 + (h->nv ? (double)h->nd / h->nv : 0.0));
+}
+
+int check_ws(plse_instance *h, int p) {
+    if (p < 2 || p > PLSE_MAX_POPULATION) return PLSE_E_ARG;
+    h->L = plan(h, p);
+    if (!h->ws || h->ws_bytes < h->L.total) return PLSE_E_WORKSPACE;
+    set_attributes_once();
     return PLSE_OK;
 }
 
-int ensure_events(plse_instance *h, size_t count) {
-    while (h->ev.size() < count) {
+// Upload tables and argument blocks of new instances (workspaces attached),
+// then build their initial populations P_1: batched launches.
+int admit(const std::vector<plse_instance *> &hs, int p, const uint64_t *seeds, hipStream_t s) {
+    for (size_t i = 0; i < hs.size(); ++i) {
+        plse_instance *h = hs[i];
+        RC_TRY(check_ws(h, p));
+        build_pipeline_args(h, p, seeds[i]);
+        RC_TRY(upload_instance(h, s));
+        RC_TRY(upload_args(h, s));
+    }
+    RC_TRY(launch_ctl(hs, true, s));
+    size_t init_lds = 0;
+    for (plse_instance *h : hs)
+        init_lds = std::max(init_lds, init_lds_bytes(dev_instance(h), next_pow2(std::max(4, h->nv))));
+    RC_TRY(launch_over(hs, &ArgBlock::init,
+                       [&](const ArgList &L, int c) { return launch_init(L, c, p, init_lds, s); }));
+    RC_TRY(launch_over(hs, &ArgBlock::pop,
+                       [&](const ArgList &L, int c) { return launch_pop_setup(L, c, s); }));
+    RC_TRY(launch_over(hs, &ArgBlock::fill,
+                       [&](const ArgList &L, int c) { return launch_fill_zero(L, c, s); }));
+    return PLSE_OK;
+}
+
+// Launch order (longest estimated work first) and the shared PLITS shape.
+void shape_session(Session &S) {
+    std::stable_sort(S.hs.begin(), S.hs.end(), [](const plse_instance *a, const plse_instance *b) {
+        return work_estimate(a) > work_estimate(b);
+    });
+    S.lds_per_wave = 0;
+    bool same_wpb = true;
+    for (plse_instance *h : S.hs) {
+        S.lds_per_wave = std::max(S.lds_per_wave, plits_lds(h).per_wave);
+        same_wpb = same_wpb && h->wpb == S.hs[0]->wpb;
+    }
+    S.wpb = (same_wpb && S.hs[0]->wpb) ? S.hs[0]->wpb : auto_wpb(S.lds_per_wave);
+    if (S.wpb * S.lds_per_wave > max_lds_per_block()) S.wpb = 1;
+}
+
+// Upload, initial population P_1 and generation graphs of a session.
+int session_begin(Session &S, const uint64_t *seeds, hipStream_t s) {
+    RC_TRY(admit(S.hs, S.p, seeds, s));
+    shape_session(S);
+    RC_TRY(capture([&](hipStream_t cs) { return enqueue_local_search(S, cs); }, &S.ls));
+    RC_TRY(capture([&](hipStream_t cs) { return enqueue_rest(S, cs); }, &S.rest));
+    S.steps = 0;
+    return PLSE_OK;
+}
+
+int session_step(Session &S, int generations, hipStream_t s) {
+    if (S.steps + generations > PLSE_MAX_GENERATIONS) return PLSE_E_ARG;
+    while (S.ev.size() < 3 * (size_t)(S.steps + generations)) {
         hipEvent_t e = nullptr;
         HIP_TRY(hipEventCreate(&e));
-        h->ev.push_back(e);
+        S.ev.push_back(e);
+    }
+    for (int g = 0; g < generations; ++g) {
+        const size_t k = 3 * (size_t)(S.steps + g);
+        HIP_TRY(hipEventRecord(S.ev[k], s));
+        HIP_TRY(hipGraphLaunch(S.ls, s));
+        HIP_TRY(hipEventRecord(S.ev[k + 1], s));
+        HIP_TRY(hipGraphLaunch(S.rest, s));
+        HIP_TRY(hipEventRecord(S.ev[k + 2], s));
+    }
+    S.steps += generations;
+    return PLSE_OK;
+}
+
+// Wait for the stream; per instance: statistics, timings and the best grid.
+int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &order,
+                int8_t *const *grids, int32_t *filled) {
+    const int G = std::max(S.steps, 1);
+    std::vector<Ctl> ctl(S.hs.size());
+    std::vector<std::vector<GenStat>> gs(S.hs.size(), std::vector<GenStat>((size_t)G));
+    std::vector<std::vector<uint8_t>> star(S.hs.size());
+    for (size_t i = 0; i < S.hs.size(); ++i) {
+        plse_instance *h = S.hs[i];
+        star[i].resize((size_t)h->stride);
+        HIP_TRY(hipMemcpyAsync(&ctl[i], at<Ctl>(h, h->L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost,
+                               s));
+        HIP_TRY(hipMemcpyAsync(gs[i].data(), at<GenStat>(h, h->L.stats), sizeof(GenStat) * G,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(star[i].data(), at<uint8_t>(h, h->L.Sstar), h->stride,
+                               hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<float> tp((size_t)S.steps), tr((size_t)S.steps);
+    for (int g = 0; g < S.steps; ++g) {
+        HIP_TRY(hipEventElapsedTime(&tp[g], S.ev[3 * g], S.ev[3 * g + 1]));
+        HIP_TRY(hipEventElapsedTime(&tr[g], S.ev[3 * g + 1], S.ev[3 * g + 2]));
+    }
+    for (size_t i = 0; i < S.hs.size(); ++i) {
+        plse_instance *h = S.hs[i];
+        const int gens = ctl[i].gens_run;
+        h->gen_best.assign((size_t)gens, 0);
+        h->gen_cnt.assign((size_t)gens * kCounters, 0);
+        plse_stats &ls = h->last;
+        std::memset(&ls, 0, sizeof(ls));
+        for (int g = 0; g < gens; ++g) {
+            h->gen_best[g] = gs[i][g].best_f;
+            for (int q = 0; q < kCounters; ++q) {
+                h->gen_cnt[(size_t)g * kCounters + q] = gs[i][g].cnt[q];
+                ls.totals[q] += gs[i][g].cnt[q];
+            }
+        }
+        ls.generations_run = gens;
+        ls.best_f = ctl[i].fstar;
+        ls.best_generation = ctl[i].best_gen;
+        h->ms_plits = tp;
+        h->ms_rest = tr;
+        // best grid: prefilled cells plus S* on the vertices
+        const size_t slot = (size_t)(std::find(order.begin(), order.end(), h) - order.begin());
+        int8_t *out = grids[slot];
+        const int n = h->n;
+        int cnt = 0;
+        for (int c = 0; c < n * n; ++c) {
+            const int v = h->cell_v[c];
+            const int8_t val =
+                (v == -1) ? h->grid[c] : ((v >= 0 && gens > 0) ? (int8_t)star[i][v] : (int8_t)0);
+            out[c] = val;
+            cnt += (val != 0);
+        }
+        filled[slot] = cnt;
     }
     return PLSE_OK;
 }
@@ -442,12 +667,25 @@ struct BusyGuard {
     }
 };
 
-int check_ws(plse_instance *h, int p, Layout *L) {
-    if (p < 2 || p > PLSE_MAX_POPULATION) return PLSE_E_ARG;
-    *L = plan(h, p);
-    if (!h->ws || h->ws_bytes < L->total) return PLSE_E_WORKSPACE;
-    set_attributes_once();
+void drop_session(plse_instance *h) {
+    delete h->own;
+    h->own = nullptr;
+    h->in_session = false;
+}
+
+// Stage calls: one instance, argument block prepared on the host.
+int stage_prepare(plse_instance *h, int p, hipStream_t s) {
+    if (h->in_session) return PLSE_E_BUSY;
+    RC_TRY(check_ws(h, p));
+    RC_TRY(upload_instance(h, s));
     return PLSE_OK;
+}
+
+template <typename M>
+ArgList single(plse_instance *h, M ArgBlock::*member) {
+    ArgList L{};
+    L.p[0] = dev_arg(h, member);
+    return L;
 }
 
 }  // namespace
@@ -503,8 +741,8 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
             h->coll[(size_t)j * n + h->colc[j]++] = (uint32_t)v | ((uint32_t)i << 16);
         }
     h->ub = (h->l == 1) ? n * n - 2 : n * n - h->l;
-    // vertex records: 128-bit domain mask, first tabu slot (sum of earlier
-    // domain sizes), coordinates
+    // vertex records: 128-bit domain mask, first slot (sum of earlier domain
+    // sizes), coordinates and domain size; domain colour lists
     h->vrec.assign((size_t)h->nv * 8, 0);
     uint32_t off = 0;
     for (int v = 0; v < h->nv; ++v) {
@@ -564,7 +802,7 @@ int plse_row_stride(plse_handle h, int32_t *stride) {
 int plse_set_param(plse_handle h, const char *key, int64_t v) {
     if (!h || !key) return PLSE_E_ARG;
     BusyGuard g(h);
-    if (!g.ok) return PLSE_E_BUSY;
+    if (!g.ok || h->in_session) return PLSE_E_BUSY;
     const std::string k(key);
     Params &P = h->P;
     if (k == "depth") {
@@ -604,10 +842,12 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "waves_per_block") {
         if (v != 0 && v != 1 && v != 2 && v != 4) return PLSE_E_PARAM;
         h->wpb = (int)v;
+    } else if (k == "fail_at_generation") {
+        if (v < 0 || v > PLSE_MAX_GENERATIONS) return PLSE_E_PARAM;
+        h->fail_at = (int)v;
     } else {
         return PLSE_E_PARAM;
     }
-    drop_graph(h);
     return PLSE_OK;
 }
 
@@ -626,7 +866,8 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "stop_at_ub") *v = P.stop_at_ub;
     else if (k == "nn_history") *v = P.hist_len;
     else if (k == "lanes_per_vertex") *v = choose_lpv(h);
-    else if (k == "waves_per_block") *v = h->wpb ? h->wpb : choose_wpb(h);
+    else if (k == "waves_per_block") *v = choose_wpb(h);
+    else if (k == "fail_at_generation") *v = h->fail_at;
     else return PLSE_E_PARAM;
     return PLSE_OK;
 }
@@ -641,8 +882,7 @@ int plse_attach_workspace(plse_handle h, void *ptr, size_t bytes) {
     if (!h) return PLSE_E_ARG;
     if (ptr && ((uintptr_t)ptr % kAlign)) return PLSE_E_ARG;
     BusyGuard g(h);
-    if (!g.ok) return PLSE_E_BUSY;
-    drop_graph(h);
+    if (!g.ok || h->in_session) return PLSE_E_BUSY;
     h->ws = reinterpret_cast<uint8_t *>(ptr);
     h->ws_bytes = ptr ? bytes : 0;
     return PLSE_OK;
@@ -652,28 +892,17 @@ int plse_begin(plse_handle h, int32_t p, uint64_t seed, void *stream) {
     if (!h) return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    Layout L;
-    int rc = check_ws(h, p, &L);
-    if (rc) return rc;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    rc = upload_instance(h, L, s);
-    if (rc) return rc;
-    Ctl *ctl = at<Ctl>(h, L.ctl);
-    HIP_TRY(launch_ctl_reset(ctl, s));
-    InitArgs ia{dev_instance(h, L), at<uint8_t>(h, L.S_all), at<int32_t>(h, L.f_all), p,
-                next_pow2(std::max(4, h->nv)), (uint32_t)seed, (uint32_t)(seed >> 32)};
-    HIP_TRY(launch_init(ia, s));
-    HIP_TRY(launch_pop_setup(p, h->stride, at<uint64_t>(h, L.uid), at<int32_t>(h, L.hc),
-                             at<uint8_t>(h, L.S_all), at<uint8_t>(h, L.S_off), s));
-    HIP_TRY(launch_fill_zero(at<uint32_t>(h, L.tabu), (size_t)p * (h->nd + h->nv), s));
-    if (!h->graph_valid || h->graph_p != p || h->graph_seed != seed) {
-        rc = capture_generation(h, L, p, seed);
-        if (rc) return rc;
+    drop_session(h);
+    Session *S = new Session();
+    S->hs = {h};
+    S->p = p;
+    const int rc = session_begin(*S, &seed, reinterpret_cast<hipStream_t>(stream));
+    if (rc) {
+        delete S;
+        return rc;
     }
+    h->own = S;
     h->in_session = true;
-    h->sess_p = p;
-    h->sess_seed = seed;
-    h->sess_steps = 0;
     return PLSE_OK;
 }
 
@@ -681,74 +910,19 @@ int plse_step(plse_handle h, int32_t generations, void *stream) {
     if (!h || generations < 0) return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    if (!h->in_session || !h->graph_valid) return PLSE_E_ARG;
-    if (h->sess_steps + generations > PLSE_MAX_GENERATIONS) return PLSE_E_ARG;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int rc = ensure_events(h, 3 * (size_t)(h->sess_steps + generations));
-    if (rc) return rc;
-    for (int g = 0; g < generations; ++g) {
-        const size_t k = 3 * (size_t)(h->sess_steps + g);
-        HIP_TRY(hipEventRecord(h->ev[k], s));
-        HIP_TRY(hipGraphLaunch(h->exec_ls, s));
-        HIP_TRY(hipEventRecord(h->ev[k + 1], s));
-        HIP_TRY(hipGraphLaunch(h->exec_rest, s));
-        HIP_TRY(hipEventRecord(h->ev[k + 2], s));
-    }
-    h->sess_steps += generations;
-    return PLSE_OK;
+    if (!h->in_session || !h->own) return PLSE_E_ARG;
+    return session_step(*h->own, generations, reinterpret_cast<hipStream_t>(stream));
 }
 
 int plse_end(plse_handle h, void *stream, int8_t *best_grid, int32_t *filled) {
     if (!h || !best_grid || !filled) return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    if (!h->in_session) return PLSE_E_ARG;
-    h->in_session = false;
-    const Layout L = plan(h, h->sess_p);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int st = h->stride;
-    const int G = std::max(h->sess_steps, 1);
-    Ctl hc{};
-    std::vector<GenStat> gs((size_t)G);
-    std::vector<uint8_t> sstar((size_t)st);
-    HIP_TRY(hipMemcpyAsync(&hc, at<Ctl>(h, L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(gs.data(), at<GenStat>(h, L.stats), sizeof(GenStat) * G,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(sstar.data(), at<uint8_t>(h, L.Sstar), st, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int gens = hc.gens_run;
-    h->gen_best.assign((size_t)gens, 0);
-    h->gen_cnt.assign((size_t)gens * kCounters, 0);
-    plse_stats &ls = h->last;
-    std::memset(&ls, 0, sizeof(ls));
-    for (int g = 0; g < gens; ++g) {
-        h->gen_best[g] = gs[g].best_f;
-        for (int q = 0; q < kCounters; ++q) {
-            h->gen_cnt[(size_t)g * kCounters + q] = gs[g].cnt[q];
-            ls.totals[q] += gs[g].cnt[q];
-        }
-    }
-    ls.generations_run = gens;
-    ls.best_f = hc.fstar;
-    ls.best_generation = hc.best_gen;
-    h->ms_plits.assign((size_t)h->sess_steps, 0.f);
-    h->ms_rest.assign((size_t)h->sess_steps, 0.f);
-    for (int g = 0; g < h->sess_steps; ++g) {
-        HIP_TRY(hipEventElapsedTime(&h->ms_plits[g], h->ev[3 * g], h->ev[3 * g + 1]));
-        HIP_TRY(hipEventElapsedTime(&h->ms_rest[g], h->ev[3 * g + 1], h->ev[3 * g + 2]));
-    }
-    // best grid: prefilled cells plus S* on the vertices
-    const int n = h->n;
-    int cnt = 0;
-    for (int c = 0; c < n * n; ++c) {
-        const int v = h->cell_v[c];
-        const int8_t val =
-            (v == -1) ? h->grid[c] : ((v >= 0 && gens > 0) ? (int8_t)sstar[v] : (int8_t)0);
-        best_grid[c] = val;
-        cnt += (val != 0);
-    }
-    *filled = cnt;
-    return PLSE_OK;
+    if (!h->in_session || !h->own) return PLSE_E_ARG;
+    int8_t *grids[1] = {best_grid};
+    const int rc = session_end(*h->own, reinterpret_cast<hipStream_t>(stream), {h}, grids, filled);
+    drop_session(h);
+    return rc;
 }
 
 int plse_solve(plse_handle h, int32_t p, int32_t G, uint64_t seed, void *stream,
@@ -758,13 +932,44 @@ int plse_solve(plse_handle h, int32_t p, int32_t G, uint64_t seed, void *stream,
     if (rc) return rc;
     rc = plse_step(h, G, stream);
     if (rc) {
-        int8_t *tmp = new int8_t[(size_t)h->n * h->n];
+        std::vector<int8_t> tmp((size_t)h->n * h->n);
         int32_t f = 0;
-        (void)plse_end(h, stream, tmp, &f);
-        delete[] tmp;
+        (void)plse_end(h, stream, tmp.data(), &f);
         return rc;
     }
     return plse_end(h, stream, best_grid, filled);
+}
+
+int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t p, int32_t G,
+                     const uint64_t *seeds, void *stream, int8_t *const *best_grids,
+                     int32_t *filled) {
+    if (!hs || count < 1 || !seeds || !best_grids || !filled || G < 1 ||
+        G > PLSE_MAX_GENERATIONS)
+        return PLSE_E_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || !best_grids[i]) return PLSE_E_ARG;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return PLSE_E_ARG;
+    }
+    std::vector<BusyGuard *> guards;
+    int rc = PLSE_OK;
+    for (int i = 0; i < count && !rc; ++i) {
+        guards.push_back(new BusyGuard(hs[i]));
+        if (!guards.back()->ok || hs[i]->in_session) rc = PLSE_E_BUSY;
+    }
+    if (!rc) {
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        Session S;
+        S.hs.assign(hs, hs + count);
+        S.p = p;
+        std::vector<plse_instance *> order(hs, hs + count);
+        std::vector<uint64_t> sd(seeds, seeds + count);
+        rc = session_begin(S, sd.data(), s);
+        if (!rc) rc = session_step(S, G, s);
+        if (!rc) rc = session_end(S, s, order, best_grids, filled);
+    }
+    for (BusyGuard *g : guards) delete g;
+    return rc;
 }
 
 int plse_last_timing(plse_handle h, int32_t *steps, float *plits_ms, float *rest_ms) {
@@ -779,17 +984,14 @@ int plse_last_stats(plse_handle h, plse_stats *out, int32_t *per_gen_best_f,
                     uint64_t *per_gen_counters) {
     if (!h || !out) return PLSE_E_ARG;
     *out = h->last;
-    if (per_gen_best_f)
-        std::copy(h->gen_best.begin(), h->gen_best.end(), per_gen_best_f);
-    if (per_gen_counters)
-        std::copy(h->gen_cnt.begin(), h->gen_cnt.end(), per_gen_counters);
+    if (per_gen_best_f) std::copy(h->gen_best.begin(), h->gen_best.end(), per_gen_best_f);
+    if (per_gen_counters) std::copy(h->gen_cnt.begin(), h->gen_cnt.end(), per_gen_counters);
     return PLSE_OK;
 }
 
 void plse_destroy(plse_handle h) {
     if (!h) return;
-    drop_graph(h);
-    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    drop_session(h);
     delete h;
 }
 
@@ -804,6 +1006,7 @@ const char *plse_strerror(int status) {
         case PLSE_PENDING: return "pending";
         case PLSE_E_PARAM: return "unknown parameter or value out of range";
         case PLSE_E_CAPACITY: return "request exceeds the server capacity";
+        case PLSE_E_FAULT: return "request ended by the fault-injection hook";
         default: return "unknown status";
     }
 }
@@ -816,15 +1019,13 @@ int plse_stage_init(plse_handle h, int32_t p, uint64_t seed, void *stream, uint8
     if (!h || !S || !f) return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    Layout L;
-    int rc = check_ws(h, p, &L);
-    if (rc) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    rc = upload_instance(h, L, s);
-    if (rc) return rc;
-    InitArgs ia{dev_instance(h, L), S, f, p, next_pow2(std::max(4, h->nv)), (uint32_t)seed,
-                (uint32_t)(seed >> 32)};
-    HIP_TRY(launch_init(ia, s));
+    RC_TRY(stage_prepare(h, p, s));
+    h->args.init = InitArgs{dev_instance(h), S, f, p, next_pow2(std::max(4, h->nv)),
+                            (uint32_t)seed, (uint32_t)(seed >> 32)};
+    RC_TRY(upload_args(h, s));
+    HIP_TRY(launch_init(single(h, &ArgBlock::init), 1, p,
+                        init_lds_bytes(h->args.init.I, h->args.init.pow2), s));
     return PLSE_OK;
 }
 
@@ -835,15 +1036,16 @@ int plse_stage_plits(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void 
         return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    Layout L;
-    int rc = check_ws(h, p, &L);
-    if (rc) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    rc = upload_instance(h, L, s);
-    if (rc) return rc;
-    PlitsArgs a = plits_args(h, L, p, gen, seed, S_in, S_out, f_out, counters, nullptr);
-    HIP_TRY(launch_fill_zero(at<uint32_t>(h, L.tabu), (size_t)p * (h->nd + h->nv), s));
-    HIP_TRY(launch_plits(a, choose_lpv(h), choose_wpb(h), s));
+    RC_TRY(stage_prepare(h, p, s));
+    h->args.plits = make_plits(h, p, gen, seed, S_in, S_out, f_out, counters, nullptr);
+    h->args.fill = FillArgs{at<uint32_t>(h, h->L.tabu), (size_t)p * (h->nd + h->nv)};
+    RC_TRY(upload_args(h, s));
+    HIP_TRY(launch_fill_zero(single(h, &ArgBlock::fill), 1, s));
+    const int wpb = choose_wpb(h);
+    if (wpb * plits_lds(h).per_wave > max_lds_per_block()) return PLSE_E_ARG;
+    HIP_TRY(launch_plits(single(h, &ArgBlock::plits), 1, p, plits_lds(h).per_wave,
+                         choose_lpv(h), wpb, s));
     return PLSE_OK;
 }
 
@@ -851,12 +1053,14 @@ int plse_stage_distances(plse_handle h, int32_t m, void *stream, const uint8_t *
     if (!h || !S || !D || m < 1) return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    Layout L;
-    int rc = check_ws(h, std::max(2, (m + 1) / 2), &L);
-    if (rc) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    HIP_TRY(launch_distances(nullptr, S, at<uint32_t>(h, L.planes), D, m, h->nv, h->stride, m,
-                             colour_bits(h->n), s));
+    RC_TRY(stage_prepare(h, std::max(2, (m + 1) / 2), s));
+    const int W = (h->nv + 31) / 32, B = colour_bits(h->n);
+    h->args.pack = PackArgs{nullptr, S, at<uint32_t>(h, h->L.planes), m, h->nv, h->stride, W, B};
+    h->args.dist = DistArgs{nullptr, at<uint32_t>(h, h->L.planes), D, m, W, m, (m + 63) / 64};
+    RC_TRY(upload_args(h, s));
+    HIP_TRY(launch_pack(single(h, &ArgBlock::pack), 1, (size_t)m * W, s));
+    HIP_TRY(launch_dist(single(h, &ArgBlock::dist), 1, m, B, s));
     return PLSE_OK;
 }
 
@@ -865,11 +1069,16 @@ int plse_stage_select(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void
     if (!h || !f_all || !D_all || !accepted || gen < 1 || gen >= (1 << 24)) return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    Layout L;
-    int rc = check_ws(h, p, &L);
-    if (rc) return rc;
-    return launch_select_stage(h, L, p, gen, seed, nullptr, f_all, D_all, 2 * p, accepted,
-                               reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    RC_TRY(stage_prepare(h, p, s));
+    const int m = 2 * p;
+    h->args.close = CloseArgs{nullptr, D_all, at<int32_t>(h, h->L.deg), at<uint16_t>(h, h->L.adj),
+                              m, m, h->nv, h->P.spacing};
+    h->args.select = make_select(h, p, gen, seed, nullptr, f_all, D_all, m, accepted);
+    RC_TRY(upload_args(h, s));
+    HIP_TRY(launch_close(single(h, &ArgBlock::close), 1, m, s));
+    HIP_TRY(launch_select(single(h, &ArgBlock::select), 1, select_lds(h, p), s));
+    return PLSE_OK;
 }
 
 int plse_stage_match(plse_handle h, int32_t p, void *stream, const int16_t *D,
@@ -878,11 +1087,18 @@ int plse_stage_match(plse_handle h, int32_t p, void *stream, const int16_t *D,
     if (!h || !D || !uid || !hist || !hcount || !partner || !dpart) return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    Layout L;
-    int rc = check_ws(h, p, &L);
-    if (rc) return rc;
-    return launch_match_stage(h, L, p, nullptr, D, p, nullptr, uid, hist, hcount, partner, dpart,
-                              reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    RC_TRY(stage_prepare(h, p, s));
+    const Layout &L = h->L;
+    h->args.hash = HashArgs{nullptr, uid, at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals), p,
+                            L.hsize};
+    h->args.match = MatchArgs{nullptr, D, nullptr, uid, hist, hcount, at<uint64_t>(h, L.hkeys),
+                              at<int32_t>(h, L.hvals), partner, dpart, p, p, L.hsize,
+                              h->P.hist_len};
+    RC_TRY(upload_args(h, s));
+    HIP_TRY(launch_hash(single(h, &ArgBlock::hash), 1, p, L.hsize, s));
+    HIP_TRY(launch_match(single(h, &ArgBlock::match), 1, p, s));
+    return PLSE_OK;
 }
 
 int plse_stage_aux(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void *stream,
@@ -892,12 +1108,347 @@ int plse_stage_aux(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void *s
         return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
-    Layout L;
-    int rc = check_ws(h, p, &L);
-    if (rc) return rc;
-    AuxArgs xa{nullptr, S, partner, dpart, S_off, p, h->nv, h->stride, gen, h->P.beta_num,
-               h->P.beta_den, (uint32_t)seed, (uint32_t)(seed >> 32)};
-    HIP_TRY(launch_aux(xa, reinterpret_cast<hipStream_t>(stream)));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    RC_TRY(stage_prepare(h, p, s));
+    h->args.aux = AuxArgs{nullptr, S, partner, dpart, S_off, p, h->nv, h->stride, gen,
+                          h->P.beta_num, h->P.beta_den, (uint32_t)seed, (uint32_t)(seed >> 32)};
+    RC_TRY(upload_args(h, s));
+    HIP_TRY(launch_aux(single(h, &ArgBlock::aux), 1, p, s));
+    return PLSE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching over a device arena (include/plse.h).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Request {
+    uint64_t ticket = 0;
+    plse_instance *h = nullptr;
+    int p = 0, G = 0;
+    uint64_t seed = 0;
+    size_t off = 0, bytes = 0;
+    int steps = 0;
+    int status = PLSE_PENDING;
+    double t_submit = 0, t_admit = -1, t_done = -1;
+    std::vector<double> t_gen;  // wall time at the end of each generation
+    std::vector<int8_t> grid;
+    int filled = 0, best_gen = 0;
+    uint64_t moves = 0;
+};
+
+// Results of one finished request (the stream is idle).
+int collect(Request &r, hipStream_t s) {
+    plse_instance *h = r.h;
+    Ctl c{};
+    std::vector<GenStat> gs((size_t)std::max(r.steps, 1));
+    std::vector<uint8_t> star((size_t)h->stride);
+    HIP_TRY(hipMemcpyAsync(&c, at<Ctl>(h, h->L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(gs.data(), at<GenStat>(h, h->L.stats), sizeof(GenStat) * gs.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(star.data(), at<uint8_t>(h, h->L.Sstar), h->stride,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int gens = c.gens_run;
+    h->gen_best.assign((size_t)gens, 0);
+    h->gen_cnt.assign((size_t)gens * kCounters, 0);
+    std::memset(&h->last, 0, sizeof(h->last));
+    for (int g = 0; g < gens; ++g) {
+        h->gen_best[g] = gs[g].best_f;
+        for (int q = 0; q < kCounters; ++q) {
+            h->gen_cnt[(size_t)g * kCounters + q] = gs[g].cnt[q];
+            h->last.totals[q] += gs[g].cnt[q];
+        }
+    }
+    h->last.generations_run = gens;
+    h->last.best_f = c.fstar;
+    h->last.best_generation = c.best_gen;
+    r.best_gen = c.best_gen;
+    r.moves = h->last.totals[C_MOVES];
+    const int n = h->n;
+    r.grid.assign((size_t)n * n, 0);
+    int cnt = 0;
+    for (int q = 0; q < n * n; ++q) {
+        const int v = h->cell_v[q];
+        const int8_t val =
+            (v == -1) ? h->grid[q] : ((v >= 0 && gens > 0) ? (int8_t)star[v] : (int8_t)0);
+        r.grid[q] = val;
+        cnt += (val != 0);
+    }
+    r.filled = cnt;
+    return PLSE_OK;
+}
+
+}  // namespace
+
+struct plse_server_s {
+    uint8_t *arena = nullptr;
+    size_t budget = 0;
+    int max_slots = 1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> waiting;
+    std::vector<Request *> resident;
+    std::map<uint64_t, Request *> finished;
+    std::map<size_t, size_t> free_blocks;  // offset -> bytes
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    // First-fit placement in the arena (256-byte granules); merge on release.
+    bool place(Request *r) {
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second >= r->bytes) {
+                r->off = it->first;
+                const size_t rest = it->second - r->bytes;
+                const size_t at2 = it->first + r->bytes;
+                free_blocks.erase(it);
+                if (rest) free_blocks[at2] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+
+    void release(Request *r) {
+        auto it = free_blocks.emplace(r->off, r->bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_blocks.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_blocks.erase(nx);
+        }
+        if (it != free_blocks.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_blocks.erase(it);
+            }
+        }
+    }
+
+    void finish(Request *r, int status) {
+        r->status = status;
+        r->t_done = now();
+        r->h->ws = nullptr;
+        r->h->ws_bytes = 0;
+        r->h->in_session = false;
+        release(r);
+        finished[r->ticket] = r;
+    }
+
+    void loop();
+};
+
+void plse_server_s::loop() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Request *> fresh;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop || !waiting.empty() || !resident.empty(); });
+            if (stop) return;
+            // admission at the generation boundary: arrival order, while the
+            // workspace fits the free arena and a slot is free
+            while (!waiting.empty() && (int)(resident.size() + fresh.size()) < max_slots) {
+                Request *r = waiting.front();
+                if (!place(r)) break;
+                waiting.pop_front();
+                r->h->ws = arena + r->off;
+                r->h->ws_bytes = r->bytes;
+                fresh.push_back(r);
+            }
+        }
+        int rc = PLSE_OK;
+        // new requests: their initial populations, grouped by population size
+        std::map<int, std::vector<Request *>> by_p;
+        for (Request *r : fresh) by_p[r->p].push_back(r);
+        for (auto &kv : by_p) {
+            std::vector<plse_instance *> hs;
+            std::vector<uint64_t> seeds;
+            for (Request *r : kv.second) {
+                hs.push_back(r->h);
+                seeds.push_back(r->seed);
+            }
+            const int e = admit(hs, kv.first, seeds.data(), stream);
+            if (e) {
+                std::lock_guard<std::mutex> lk(mu);
+                for (Request *r : kv.second) finish(r, e);
+                for (Request *r : kv.second) fresh.erase(std::find(fresh.begin(), fresh.end(), r));
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            const double t = now();
+            for (Request *r : fresh) {
+                r->t_admit = t;
+                resident.push_back(r);
+            }
+        }
+        // one generation of every resident request, grouped by population size
+        std::vector<Request *> run;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            run = resident;
+        }
+        std::map<int, std::vector<plse_instance *>> groups;
+        for (Request *r : run) groups[r->p].push_back(r->h);
+        for (auto &kv : groups) {
+            Session S;
+            S.hs = kv.second;
+            S.p = kv.first;
+            shape_session(S);
+            if (!rc) rc = enqueue_local_search(S, stream);
+            if (!rc) rc = enqueue_rest(S, stream);
+        }
+        if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = PLSE_E_HIP;
+        const double t = now();
+        std::vector<Request *> done;
+        for (Request *r : run) {
+            r->steps += 1;
+            r->t_gen.push_back(t);
+            if (rc || r->steps >= r->G || (r->h->fail_at && r->steps >= r->h->fail_at))
+                done.push_back(r);
+        }
+        std::vector<int> st(done.size(), rc);
+        for (size_t i = 0; i < done.size(); ++i) {
+            if (!rc && done[i]->h->fail_at && done[i]->steps >= done[i]->h->fail_at &&
+                done[i]->steps < done[i]->G)
+                st[i] = PLSE_E_FAULT;
+            else if (!rc)
+                st[i] = collect(*done[i], stream);
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (size_t i = 0; i < done.size(); ++i) {
+                resident.erase(std::find(resident.begin(), resident.end(), done[i]));
+                finish(done[i], st[i]);
+            }
+        }
+    }
+}
+
+extern "C" {
+
+int plse_server_create(size_t budget, void *device_ptr, int32_t max_slots, void *stream,
+                       plse_server *out) {
+    if (!out || !device_ptr || budget == 0 || max_slots < 1 || ((uintptr_t)device_ptr % kAlign))
+        return PLSE_E_ARG;
+    plse_server_s *s = new plse_server_s();
+    s->arena = reinterpret_cast<uint8_t *>(device_ptr);
+    s->budget = budget / kAlign * kAlign;
+    s->max_slots = max_slots;
+    s->stream = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetDevice(&s->device);
+    s->t0 = std::chrono::steady_clock::now();
+    s->free_blocks[0] = s->budget;
+    set_attributes_once();
+    s->worker = std::thread([s] { s->loop(); });
+    *out = s;
+    return PLSE_OK;
+}
+
+int plse_server_submit(plse_server s, plse_handle h, int32_t p, int32_t G, uint64_t seed,
+                       uint64_t *ticket) {
+    if (!s || !h || !ticket || p < 2 || p > PLSE_MAX_POPULATION || G < 1 ||
+        G > PLSE_MAX_GENERATIONS)
+        return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok || h->in_session) return PLSE_E_BUSY;
+    Request *r = new Request();
+    r->h = h;
+    r->p = p;
+    r->G = G;
+    r->seed = seed;
+    r->bytes = round_up(plan(h, p).total, kAlign);
+    if (r->bytes > s->budget) {
+        delete r;
+        return PLSE_E_CAPACITY;
+    }
+    h->in_session = true;  // the server owns the handle until it is polled
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    r->t_submit = s->now();
+    *ticket = r->ticket;
+    s->waiting.push_back(r);
+    s->cv.notify_one();
+    return PLSE_OK;
+}
+
+int plse_server_poll(plse_server s, uint64_t ticket, int8_t *best_grid, int32_t *filled,
+                     plse_timing *t) {
+    if (!s) return PLSE_E_ARG;
+    Request *r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->finished.find(ticket);
+        if (it == s->finished.end()) {
+            for (Request *q : s->waiting)
+                if (q->ticket == ticket) return PLSE_PENDING;
+            for (Request *q : s->resident)
+                if (q->ticket == ticket) return PLSE_PENDING;
+            return PLSE_E_ARG;
+        }
+        r = it->second;
+        s->finished.erase(it);
+    }
+    if (best_grid && !r->grid.empty()) std::memcpy(best_grid, r->grid.data(), r->grid.size());
+    if (filled) *filled = r->filled;
+    if (t) {
+        t->submit_s = r->t_submit;
+        t->admit_s = r->t_admit;
+        t->done_s = r->t_done;
+        t->best_s = (r->best_gen >= 1 && r->best_gen <= (int)r->t_gen.size())
+                        ? r->t_gen[r->best_gen - 1]
+                        : r->t_done;
+        t->generations = r->steps;
+        t->best_generation = r->best_gen;
+        t->filled = r->filled;
+        t->status = r->status;
+        t->moves = r->moves;
+    }
+    const int st = r->status;
+    delete r;
+    return st;
+}
+
+int plse_server_status(plse_server s, int32_t *waiting, int32_t *resident, int32_t *finished) {
+    if (!s) return PLSE_E_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (waiting) *waiting = (int32_t)s->waiting.size();
+    if (resident) *resident = (int32_t)s->resident.size();
+    if (finished) *finished = (int32_t)s->finished.size();
+    return PLSE_OK;
+}
+
+int plse_server_destroy(plse_server s) {
+    if (!s) return PLSE_E_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (Request *r : s->waiting) {
+        r->h->in_session = false;
+        delete r;
+    }
+    for (Request *r : s->resident) {
+        r->h->in_session = false;
+        r->h->ws = nullptr;
+        delete r;
+    }
+    for (auto &kv : s->finished) delete kv.second;
+    delete s;
     return PLSE_OK;
 }
 

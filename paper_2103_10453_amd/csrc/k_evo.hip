@@ -11,7 +11,8 @@ namespace plse {
 // ---------------------------------------------------------------------------
 // control
 // ---------------------------------------------------------------------------
-__global__ void ctl_reset_kernel(Ctl *ctl) {
+__global__ void ctl_reset_kernel(const ArgList L) {
+    Ctl *ctl = static_cast<Ctl *>(const_cast<void *>(L.p[blockIdx.y]));
     if (threadIdx.x == 0) {
         ctl->gen = 0;
         ctl->stop = 0;
@@ -21,22 +22,23 @@ __global__ void ctl_reset_kernel(Ctl *ctl) {
     }
 }
 
-__global__ void gen_begin_kernel(Ctl *ctl) {
+__global__ void gen_begin_kernel(const ArgList L) {
+    Ctl *ctl = static_cast<Ctl *>(const_cast<void *>(L.p[blockIdx.y]));
     if (threadIdx.x == 0 && !ctl->stop) ctl->gen += 1;
 }
 
 // Fresh population bookkeeping: uid = slot, empty partner history, and the
 // first offspring population is the initial population itself (Alg. 2).
-__global__ void pop_setup_kernel(int32_t p, int32_t stride, uint64_t *uid, int32_t *hc,
-                                 const uint8_t *S, uint8_t *S_off) {
+__global__ void pop_setup_kernel(const ArgList L) {
+    const PopSetupArgs a = arg_of<PopSetupArgs>(L);
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (size_t)p) {
-        uid[i] = i;
-        hc[i] = 0;
+    if (i < (size_t)a.p) {
+        a.uid[i] = i;
+        a.hc[i] = 0;
     }
-    const size_t nq = (size_t)p * (stride >> 4);
+    const size_t nq = (size_t)a.p * (a.stride >> 4);
     for (size_t q = i; q < nq; q += (size_t)gridDim.x * blockDim.x)
-        reinterpret_cast<uint4 *>(S_off)[q] = reinterpret_cast<const uint4 *>(S)[q];
+        reinterpret_cast<uint4 *>(a.S_off)[q] = reinterpret_cast<const uint4 *>(a.S)[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -45,7 +47,8 @@ __global__ void pop_setup_kernel(int32_t p, int32_t stride, uint64_t *uid, int32
 // per-individual counters of the generation and sets the bound stop flag.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(1024) void best_kernel(const BestArgs a) {
+__global__ __launch_bounds__(1024) void best_kernel(const ArgList L) {
+    const BestArgs a = arg_of<BestArgs>(L);
     if (a.ctl->stop) return;
     const int g = a.ctl->gen;
     __shared__ uint64_t kmin[16];
@@ -105,7 +108,8 @@ __global__ __launch_bounds__(1024) void best_kernel(const BestArgs a) {
 // some plane differs, so D = sum_w popcount(OR_b (a_b XOR c_b)).
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void pack_kernel(const PackArgs a) {
+__global__ __launch_bounds__(256) void pack_kernel(const ArgList L) {
+    const PackArgs a = arg_of<PackArgs>(L);
     if (a.ctl && a.ctl->stop) return;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)a.m * a.W) return;
@@ -131,7 +135,8 @@ constexpr int kCW = 8;      // words of 32 vertices staged per step
 // block of pairs (rows ty+16i, columns tx+16j).  Both D[I][J] and its mirror
 // are written through an LDS staging tile so that stores are row-contiguous.
 template <int B>
-__global__ __launch_bounds__(256) void dist_kernel(const DistArgs a) {
+__global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
+    const DistArgs a = arg_of<DistArgs>(L);
     if (a.ctl && a.ctl->stop) return;
     constexpr int PITCH = kCW * B + 1;  // odd pitch: rows fall in distinct banks
     __shared__ uint32_t As[kTile * PITCH];
@@ -208,30 +213,6 @@ __global__ __launch_bounds__(256) void dist_kernel(const DistArgs a) {
     }
 }
 
-hipError_t launch_distances(const Ctl *ctl, const uint8_t *S, uint32_t *planes, int16_t *D,
-                            int m, int nv, int stride, int ld, int B, hipStream_t stream) {
-    const int W = (nv + 31) / 32;
-    PackArgs pa{ctl, S, planes, m, nv, stride, W, B};
-    const size_t nt = (size_t)m * W;
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, pa);
-    const int nt1 = (m + kTile - 1) / kTile;
-    DistArgs da{ctl, planes, D, m, W, ld, nt1};
-    const unsigned ntri = (unsigned)((long)nt1 * (nt1 + 1) / 2);
-    switch (B) {
-#define PLSE_DIST_CASE(b) \
-    case b: hipLaunchKernelGGL(dist_kernel<b>, dim3(ntri), dim3(256), 0, stream, da); break;
-        PLSE_DIST_CASE(1)
-        PLSE_DIST_CASE(2)
-        PLSE_DIST_CASE(3)
-        PLSE_DIST_CASE(4)
-        PLSE_DIST_CASE(5)
-        PLSE_DIST_CASE(6)
-        PLSE_DIST_CASE(7)
-#undef PLSE_DIST_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // Population update (Alg. 4)
@@ -239,7 +220,8 @@ hipError_t launch_distances(const Ctl *ctl, const uint8_t *S, uint32_t *planes, 
 // close lists: for candidate x, the candidates y != x with spacing*D(x,y) <= |V|
 // (those x excludes once accepted); deg[x] counts them, adj keeps the first kAdj.
 
-__global__ __launch_bounds__(256) void close_kernel(const CloseArgs a) {
+__global__ __launch_bounds__(256) void close_kernel(const ArgList L) {
+    const CloseArgs a = arg_of<CloseArgs>(L);
     if (a.ctl && a.ctl->stop) return;
     const int x = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (x >= a.m) return;
@@ -264,8 +246,9 @@ __global__ __launch_bounds__(256) void close_kernel(const CloseArgs a) {
 // union of the close lists of accepted candidates) lives in an LDS bitmap.
 // Lanes take 64 candidates at a time: the candidates up to the first
 // unblocked one with a non-empty close list are decided together.
-__global__ __launch_bounds__(1024) void select_kernel(const SelectArgs a) {
+__global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
+    const SelectArgs a = arg_of<SelectArgs>(L);
     int gen = a.gen_fixed;
     if (gen == 0) {
         if (a.ctl->stop) return;
@@ -369,22 +352,14 @@ size_t select_lds_bytes(int m, int pow2, bool keys_in_lds) {
     return b + (keys_in_lds ? (size_t)pow2 * 8 : 0);
 }
 
-hipError_t launch_select(const SelectArgs &a, hipStream_t stream) {
-    const size_t lds = select_lds_bytes(a.m, a.pow2, a.keys_in_lds != 0);
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), lds, stream, a);
-    return hipGetLastError();
-}
 
-hipError_t launch_close(const CloseArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(close_kernel, dim3((a.m + 3) / 4), dim3(256), 0, stream, a);
-    return hipGetLastError();
-}
 
 // New population P_{t+1} = accepted candidates in acceptance order: rows,
 // f, uid ((gen << 32) | slot for members of P'), partner history (empty for
 // members of P').  Written to the tmp arrays, then copied back.
 
-__global__ __launch_bounds__(256) void gather_kernel(const GatherArgs a) {
+__global__ __launch_bounds__(256) void gather_kernel(const ArgList L) {
+    const GatherArgs a = arg_of<GatherArgs>(L);
     if (a.ctl->stop) return;
     const int r = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (r >= a.p) return;
@@ -402,7 +377,8 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherArgs a) {
     if (old) a.hist_tmp[(size_t)r * kHist + lane] = a.hist[(size_t)x * kHist + lane];
 }
 
-__global__ __launch_bounds__(256) void copyback_kernel(const GatherArgs a) {
+__global__ __launch_bounds__(256) void copyback_kernel(const ArgList L) {
+    const GatherArgs a = arg_of<GatherArgs>(L);
     if (a.ctl->stop) return;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t nq = (size_t)a.p * (a.stride >> 4);
@@ -419,11 +395,6 @@ __global__ __launch_bounds__(256) void copyback_kernel(const GatherArgs a) {
     }
 }
 
-hipError_t launch_gather(const GatherArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(gather_kernel, dim3((a.p + 3) / 4), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(copyback_kernel, dim3(1024), dim3(256), 0, stream, a);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // Parent matching (Section 3.5.1): nearest neighbour (D, then slot) among the
@@ -438,13 +409,15 @@ __device__ __forceinline__ uint32_t hash_uid(uint64_t u) {
 }
 
 
-__global__ void hash_clear_kernel(const HashArgs a) {
+__global__ void hash_clear_kernel(const ArgList L) {
+    const HashArgs a = arg_of<HashArgs>(L);
     if (a.ctl && a.ctl->stop) return;
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     for (int q = t; q < a.hsize; q += gridDim.x * blockDim.x) a.hkeys[q] = ~0ull;
 }
 
-__global__ void hash_insert_kernel(const HashArgs a) {
+__global__ void hash_insert_kernel(const ArgList L) {
+    const HashArgs a = arg_of<HashArgs>(L);
     if (a.ctl && a.ctl->stop) return;
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= a.p) return;
@@ -462,8 +435,9 @@ __global__ void hash_insert_kernel(const HashArgs a) {
 }
 
 
-__global__ __launch_bounds__(256) void match_kernel(const MatchArgs a) {
+__global__ __launch_bounds__(256) void match_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
+    const MatchArgs a = arg_of<MatchArgs>(L);
     if (a.ctl && a.ctl->stop) return;
     const int wv = (int)(threadIdx.x >> 6), lane = lane_id();
     const int i = (int)blockIdx.x * 4 + wv;
@@ -517,13 +491,6 @@ __global__ __launch_bounds__(256) void match_kernel(const MatchArgs a) {
     }
 }
 
-hipError_t launch_match(const HashArgs &h, const MatchArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(hash_clear_kernel, dim3((h.hsize + 255) / 256), dim3(256), 0, stream, h);
-    hipLaunchKernelGGL(hash_insert_kernel, dim3((h.p + 255) / 256), dim3(256), 0, stream, h);
-    const size_t lds = (size_t)4 * ((a.p + 31) / 32) * 4;
-    hipLaunchKernelGGL(match_kernel, dim3((a.p + 3) / 4), dim3(256), lds, stream, a);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // AUX crossover (Alg. 5): vertex v keeps S_i(v) when its XOVER draw is below
@@ -532,7 +499,8 @@ hipError_t launch_match(const HashArgs &h, const MatchArgs &a, hipStream_t strea
 // vertices per lane step (one Philox block).
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void aux_kernel(const AuxArgs a) {
+__global__ __launch_bounds__(256) void aux_kernel(const ArgList L) {
+    const AuxArgs a = arg_of<AuxArgs>(L);
     int gen = a.gen_fixed;
     if (gen == 0) {
         if (a.ctl->stop) return;
@@ -568,30 +536,87 @@ __global__ __launch_bounds__(256) void aux_kernel(const AuxArgs a) {
     }
 }
 
-hipError_t launch_aux(const AuxArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(aux_kernel, dim3((a.p + 3) / 4), dim3(256), 0, stream, a);
+
+
+
+
+
+hipError_t launch_ctl_reset(const ArgList &L, int count, hipStream_t stream) {
+    hipLaunchKernelGGL(ctl_reset_kernel, dim3(1, count), dim3(64), 0, stream, L);
     return hipGetLastError();
 }
 
-hipError_t launch_best(const BestArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, stream, a);
+hipError_t launch_gen_begin(const ArgList &L, int count, hipStream_t stream) {
+    hipLaunchKernelGGL(gen_begin_kernel, dim3(1, count), dim3(64), 0, stream, L);
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t stream) {
-    hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, stream, ctl);
+hipError_t launch_pop_setup(const ArgList &L, int count, hipStream_t stream) {
+    hipLaunchKernelGGL(pop_setup_kernel, dim3(512, count), dim3(256), 0, stream, L);
     return hipGetLastError();
 }
 
-hipError_t launch_gen_begin(Ctl *ctl, hipStream_t stream) {
-    hipLaunchKernelGGL(gen_begin_kernel, dim3(1), dim3(64), 0, stream, ctl);
+hipError_t launch_best(const ArgList &L, int count, hipStream_t stream) {
+    hipLaunchKernelGGL(best_kernel, dim3(1, count), dim3(1024), 0, stream, L);
     return hipGetLastError();
 }
 
-hipError_t launch_pop_setup(int p, int stride, uint64_t *uid, int32_t *hc, const uint8_t *S,
-                            uint8_t *S_off, hipStream_t stream) {
-    hipLaunchKernelGGL(pop_setup_kernel, dim3(1024), dim3(256), 0, stream, p, stride, uid, hc, S,
-                       S_off);
+hipError_t launch_pack(const ArgList &L, int count, size_t max_threads, hipStream_t stream) {
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((max_threads + 255) / 256), count), dim3(256),
+                       0, stream, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist(const ArgList &L, int count, int m, int B, hipStream_t stream) {
+    const int nt1 = (m + kTile - 1) / kTile;
+    const dim3 grid((unsigned)((long)nt1 * (nt1 + 1) / 2), count);
+    switch (B) {
+#define PLSE_DIST_CASE(b) \
+    case b: hipLaunchKernelGGL(dist_kernel<b>, grid, dim3(256), 0, stream, L); break;
+        PLSE_DIST_CASE(1)
+        PLSE_DIST_CASE(2)
+        PLSE_DIST_CASE(3)
+        PLSE_DIST_CASE(4)
+        PLSE_DIST_CASE(5)
+        PLSE_DIST_CASE(6)
+        PLSE_DIST_CASE(7)
+#undef PLSE_DIST_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_close(const ArgList &L, int count, int m, hipStream_t stream) {
+    hipLaunchKernelGGL(close_kernel, dim3((m + 3) / 4, count), dim3(256), 0, stream, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const ArgList &L, int count, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL(select_kernel, dim3(1, count), dim3(1024), lds, stream, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const ArgList &L, int count, int p, hipStream_t stream) {
+    hipLaunchKernelGGL(gather_kernel, dim3((p + 3) / 4, count), dim3(256), 0, stream, L);
+    hipLaunchKernelGGL(copyback_kernel, dim3(256, count), dim3(256), 0, stream, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(const ArgList &L, int count, int p, int hsize, hipStream_t stream) {
+    hipLaunchKernelGGL(hash_clear_kernel, dim3((hsize + 255) / 256, count), dim3(256), 0, stream,
+                       L);
+    hipLaunchKernelGGL(hash_insert_kernel, dim3((p + 255) / 256, count), dim3(256), 0, stream, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_match(const ArgList &L, int count, int p, hipStream_t stream) {
+    const size_t lds = (size_t)4 * ((p + 31) / 32) * 4;
+    hipLaunchKernelGGL(match_kernel, dim3((p + 3) / 4, count), dim3(256), lds, stream, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_aux(const ArgList &L, int count, int p, hipStream_t stream) {
+    hipLaunchKernelGGL(aux_kernel, dim3((p + 3) / 4, count), dim3(256), 0, stream, L);
     return hipGetLastError();
 }
 

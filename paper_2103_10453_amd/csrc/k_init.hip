@@ -10,8 +10,9 @@
 namespace plse {
 
 
-__global__ __launch_bounds__(256) void init_kernel(const InitArgs a) {
+__global__ __launch_bounds__(256) void init_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
+    const InitArgs a = arg_of<InitArgs>(L);
     const DevInstance &I = a.I;
     const int ind = (int)blockIdx.x;
     const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
@@ -109,9 +110,8 @@ size_t init_lds_bytes(const DevInstance &I, int pow2) {
     return (size_t)pow2 * 8 + (size_t)4 * I.n * 8 + (size_t)I.stride;
 }
 
-hipError_t launch_init(const InitArgs &a, hipStream_t stream) {
-    const size_t lds = init_lds_bytes(a.I, a.pow2);
-    hipLaunchKernelGGL(init_kernel, dim3(a.p), dim3(256), lds, stream, a);
+hipError_t launch_init(const ArgList &L, int count, int p, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL(init_kernel, dim3(p, count), dim3(256), lds, stream, L);
     return hipGetLastError();
 }
 

@@ -381,8 +381,9 @@ __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Sc
 }  // namespace
 
 template <int LPV>
-__global__ __launch_bounds__(256) void plits_kernel(const PlitsArgs a) {
+__global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
+    const PlitsArgs a = arg_of<PlitsArgs>(L);
     const int wv = (int)(threadIdx.x >> 6);
     const int ind = (int)blockIdx.x * (int)(blockDim.x >> 6) + wv;
     if (ind >= a.p) return;
@@ -432,31 +433,32 @@ __global__ __launch_bounds__(256) void plits_kernel(const PlitsArgs a) {
 }
 
 // Zero a tabu region (a fresh workspace, before the first phase uses it).
-__global__ void fill_zero_kernel(uint32_t *p, size_t n) {
+__global__ void fill_zero_kernel(const ArgList L) {
+    const FillArgs a = arg_of<FillArgs>(L);
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t nq = n / 4;
+    const size_t nq = a.n / 4;
     for (size_t i = t; i < nq; i += (size_t)gridDim.x * blockDim.x)
-        reinterpret_cast<uint4 *>(p)[i] = make_uint4(0u, 0u, 0u, 0u);
-    for (size_t i = nq * 4 + t; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+        reinterpret_cast<uint4 *>(a.p)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t i = nq * 4 + t; i < a.n; i += (size_t)gridDim.x * blockDim.x) a.p[i] = 0u;
 }
 
-hipError_t launch_plits(const PlitsArgs &a, int lanes_per_vertex, int waves_per_block,
-                        hipStream_t stream) {
-    const int blocks = (a.p + waves_per_block - 1) / waves_per_block;
-    const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
-    const dim3 grid(blocks), block(64 * waves_per_block);
+hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
+                        int lanes_per_vertex, int waves_per_block, hipStream_t stream) {
+    const int blocks = (p + waves_per_block - 1) / waves_per_block;
+    const size_t lds = (size_t)lds_per_wave * waves_per_block;
+    const dim3 grid(blocks, count), block(64 * waves_per_block);
     switch (lanes_per_vertex) {
-        case 1: hipLaunchKernelGGL(plits_kernel<1>, grid, block, lds, stream, a); break;
-        case 2: hipLaunchKernelGGL(plits_kernel<2>, grid, block, lds, stream, a); break;
-        case 4: hipLaunchKernelGGL(plits_kernel<4>, grid, block, lds, stream, a); break;
-        case 8: hipLaunchKernelGGL(plits_kernel<8>, grid, block, lds, stream, a); break;
+        case 1: hipLaunchKernelGGL(plits_kernel<1>, grid, block, lds, stream, L); break;
+        case 2: hipLaunchKernelGGL(plits_kernel<2>, grid, block, lds, stream, L); break;
+        case 4: hipLaunchKernelGGL(plits_kernel<4>, grid, block, lds, stream, L); break;
+        case 8: hipLaunchKernelGGL(plits_kernel<8>, grid, block, lds, stream, L); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t stream) {
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, stream, p, n);
+hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024, count), dim3(256), 0, stream, L);
     return hipGetLastError();
 }
 

@@ -9,6 +9,31 @@
 
 namespace plse {
 
+// One launch serves up to kMaxLaunch instances: blockIdx.y selects the
+// instance, whose argument block lives in its own workspace.
+constexpr int kMaxLaunch = 128;
+struct ArgList {
+    const void *p[kMaxLaunch];
+};
+
+template <typename T>
+__device__ __forceinline__ T arg_of(const ArgList &L) {
+    return *static_cast<const T *>(L.p[blockIdx.y]);
+}
+
+struct FillArgs {
+    uint32_t *p;
+    size_t n;
+};
+
+struct PopSetupArgs {
+    int32_t p, stride;
+    uint64_t *uid;
+    int32_t *hc;
+    const uint8_t *S;
+    uint8_t *S_off;
+};
+
 struct PlitsArgs {
     DevInstance I;
     Params P;
@@ -127,26 +152,28 @@ struct AuxArgs {
     uint32_t seed_lo, seed_hi;
 };
 
-hipError_t launch_plits(const PlitsArgs &a, int lanes_per_vertex, int waves_per_block,
-                        hipStream_t stream);
-hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t stream);
+// Launch entry points: `L` lists the argument blocks (device addresses) of
+// `count` instances; grid.y = count.
+hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
+                        int lanes_per_vertex, int waves_per_block, hipStream_t stream);
+hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream);
 hipError_t plits_set_lds_limit(int bytes);
-hipError_t launch_init(const InitArgs &a, hipStream_t stream);
+hipError_t launch_init(const ArgList &L, int count, int p, size_t lds, hipStream_t stream);
 size_t init_lds_bytes(const DevInstance &I, int pow2);
 hipError_t init_set_lds_limit(int bytes);
-hipError_t launch_best(const BestArgs &a, hipStream_t stream);
-hipError_t launch_distances(const Ctl *ctl, const uint8_t *S, uint32_t *planes, int16_t *D,
-                            int m, int nv, int stride, int ld, int B, hipStream_t stream);
-hipError_t launch_close(const CloseArgs &a, hipStream_t stream);
-hipError_t launch_select(const SelectArgs &a, hipStream_t stream);
+hipError_t launch_best(const ArgList &L, int count, hipStream_t stream);
+hipError_t launch_pack(const ArgList &L, int count, size_t max_threads, hipStream_t stream);
+hipError_t launch_dist(const ArgList &L, int count, int m, int B, hipStream_t stream);
+hipError_t launch_close(const ArgList &L, int count, int m, hipStream_t stream);
+hipError_t launch_select(const ArgList &L, int count, size_t lds, hipStream_t stream);
 size_t select_lds_bytes(int m, int pow2, bool keys_in_lds);
-hipError_t launch_gather(const GatherArgs &a, hipStream_t stream);
-hipError_t launch_match(const HashArgs &h, const MatchArgs &a, hipStream_t stream);
-hipError_t launch_aux(const AuxArgs &a, hipStream_t stream);
-hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t stream);
-hipError_t launch_gen_begin(Ctl *ctl, hipStream_t stream);
-hipError_t launch_pop_setup(int p, int stride, uint64_t *uid, int32_t *hc, const uint8_t *S,
-                            uint8_t *S_off, hipStream_t stream);
+hipError_t launch_gather(const ArgList &L, int count, int p, hipStream_t stream);
+hipError_t launch_hash(const ArgList &L, int count, int p, int hsize, hipStream_t stream);
+hipError_t launch_match(const ArgList &L, int count, int p, hipStream_t stream);
+hipError_t launch_aux(const ArgList &L, int count, int p, hipStream_t stream);
+hipError_t launch_ctl_reset(const ArgList &L, int count, hipStream_t stream);
+hipError_t launch_gen_begin(const ArgList &L, int count, hipStream_t stream);
+hipError_t launch_pop_setup(const ArgList &L, int count, hipStream_t stream);
 hipError_t evo_set_lds_limit(int bytes);
 
 }  // namespace plse

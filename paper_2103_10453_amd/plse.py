@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libplse.so")
 
 PLSE_OK, PLSE_E_ARG, PLSE_E_GRID, PLSE_E_WORKSPACE, PLSE_E_HIP, PLSE_E_BUSY, PLSE_PENDING, \
-    PLSE_E_PARAM, PLSE_E_CAPACITY = range(9)
+    PLSE_E_PARAM, PLSE_E_CAPACITY, PLSE_E_FAULT = range(10)
 NCOUNTERS = 8
 COUNTER_NAMES = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs"]
 HIST = 64
@@ -34,6 +34,14 @@ class Stats(ctypes.Structure):
     _fields_ = [("generations_run", ctypes.c_int32), ("best_f", ctypes.c_int32),
                 ("best_generation", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("totals", ctypes.c_uint64 * NCOUNTERS)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("best_s", ctypes.c_double),
+                ("generations", ctypes.c_int32), ("best_generation", ctypes.c_int32),
+                ("filled", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("moves", ctypes.c_uint64)]
 
 
 _LIB = None
@@ -58,6 +66,7 @@ def _lib():
             "plse_attach_workspace": [P, P, sz],
             "plse_solve": [P, i32, i32, u64, P, P, P],
             "plse_begin": [P, i32, u64, P],
+            "plse_solve_batch": [P, i32, i32, i32, P, P, P, P],
             "plse_step": [P, i32, P],
             "plse_end": [P, P, P, P],
             "plse_last_timing": [P, P, P, P],
@@ -68,6 +77,11 @@ def _lib():
             "plse_stage_select": [P, i32, i32, u64, P, P, P, P],
             "plse_stage_match": [P, i32, P, P, P, P, P, P, P],
             "plse_stage_aux": [P, i32, i32, u64, P, P, P, P, P],
+            "plse_server_create": [sz, P, i32, P, P],
+            "plse_server_submit": [P, P, i32, i32, u64, P],
+            "plse_server_poll": [P, u64, P, P, P],
+            "plse_server_status": [P, P, P, P],
+            "plse_server_destroy": [P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -89,10 +103,13 @@ def exported_symbols():
     """Names of the C-ABI functions the binding resolves."""
     L = _lib()
     names = ["plse_create", "plse_info", "plse_sizes", "plse_row_stride", "plse_set_param", "plse_get_param",
-             "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_begin",
+             "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
+             "plse_begin",
              "plse_step", "plse_end", "plse_last_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
-             "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux"]
+             "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux",
+             "plse_server_create", "plse_server_submit", "plse_server_poll", "plse_server_status",
+             "plse_server_destroy"]
     return [n for n in names if hasattr(L, n)]
 
 
@@ -178,6 +195,20 @@ def plse_solve(h, n: int, population: int, generations: int, seed: int, stream=N
     _check(_lib().plse_solve(h, population, generations, seed & ((1 << 64) - 1), _stream(stream),
                              _np(grid), ctypes.byref(filled)), "plse_solve")
     return grid, filled.value
+
+
+def plse_solve_batch(handles, ns, population: int, generations: int, seeds, stream=None):
+    """Solve several instances in one batched run; returns [(grid, filled)]."""
+    count = len(handles)
+    hs = (ctypes.c_void_p * count)(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                     for h in handles])
+    sd = (ctypes.c_uint64 * count)(*[s & ((1 << 64) - 1) for s in seeds])
+    grids = [np.zeros((n, n), dtype=np.int8) for n in ns]
+    gp = (ctypes.c_void_p * count)(*[g.ctypes.data for g in grids])
+    filled = np.zeros(count, dtype=np.int32)
+    _check(_lib().plse_solve_batch(hs, count, population, generations, sd, _stream(stream), gp,
+                                   _np(filled)), "plse_solve_batch")
+    return [(grids[i], int(filled[i])) for i in range(count)]
 
 
 def plse_begin(h, population: int, seed: int, stream=None):
@@ -314,6 +345,14 @@ class Solver:
     def stats(self):
         return plse_last_stats(self.h)
 
+    @staticmethod
+    def solve_batch(solvers, population: int, generations: int, seeds, stream=None):
+        """Batched plse_solve over several Solver objects (one workspace each)."""
+        for s in solvers:
+            s.ensure_workspace(population)
+        return plse_solve_batch([s.h for s in solvers], [s.n for s in solvers], population,
+                                generations, seeds, stream)
+
     # stage helpers returning torch tensors
     def new_pop(self, count: int):
         import torch
@@ -368,3 +407,84 @@ class Solver:
         S_off = self.new_pop(p)
         plse_stage_aux(self.h, p, gen, seed, S, partner, dpart, S_off)
         return S_off
+
+
+# --- serving ---------------------------------------------------------------------------
+def plse_server_create(budget_bytes: int, arena, max_slots: int, stream):
+    srv = ctypes.c_void_p()
+    _check(_lib().plse_server_create(budget_bytes, _dev(arena), max_slots, _stream(stream),
+                                     ctypes.byref(srv)), "plse_server_create")
+    return srv
+
+
+def plse_server_submit(srv, h, population: int, generations: int, seed: int) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib().plse_server_submit(srv, h, population, generations, seed & ((1 << 64) - 1),
+                                     ctypes.byref(t)), "plse_server_submit")
+    return t.value
+
+
+def plse_server_poll(srv, ticket: int, n: int):
+    """None while pending, else (status, grid, filled, Timing)."""
+    grid = np.zeros((n, n), dtype=np.int8)
+    filled = ctypes.c_int32()
+    t = Timing()
+    st = _lib().plse_server_poll(srv, ticket, _np(grid), ctypes.byref(filled), ctypes.byref(t))
+    if st == PLSE_PENDING:
+        return None
+    if st == PLSE_E_ARG:
+        raise PlseError(st, "plse_server_poll")
+    return st, grid, filled.value, t
+
+
+def plse_server_status(srv):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib().plse_server_status(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "plse_server_status")
+    return a.value, b.value, c.value
+
+
+def plse_server_destroy(srv):
+    if srv:
+        _lib().plse_server_destroy(srv)
+
+
+class Server:
+    """Continuous-batching server on a torch-owned device arena."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, device="cuda"):
+        import torch
+        self.arena = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.Stream(device=device)
+        self.srv = plse_server_create(budget_bytes, self.arena, max_slots, self.stream)
+        self.live = {}
+
+    def submit(self, solver, population: int, generations: int, seed: int) -> int:
+        t = plse_server_submit(self.srv, solver.h, population, generations, seed)
+        self.live[t] = solver
+        return t
+
+    def poll(self, ticket: int):
+        solver = self.live[ticket]
+        r = plse_server_poll(self.srv, ticket, solver.n)
+        if r is None:
+            return None
+        del self.live[ticket]
+        st, grid, filled, t = r
+        return dict(status=st, grid=grid, filled=filled, submit_s=t.submit_s, admit_s=t.admit_s,
+                    done_s=t.done_s, best_s=t.best_s, generations=t.generations,
+                    best_generation=t.best_generation, moves=int(t.moves))
+
+    def status(self):
+        return plse_server_status(self.srv)
+
+    def close(self):
+        if self.srv:
+            plse_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

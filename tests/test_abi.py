@@ -105,3 +105,32 @@ def test_workspace_planning_and_missing_workspace():
         assert e.value.status == P.PLSE_E_ARG
     finally:
         P.plse_destroy(h)
+
+
+def test_batch_argument_errors():
+    g = gen.planted(10, 0.4, 0)
+    h1, h2 = P.plse_create(g), P.plse_create(g)
+    try:
+        with pytest.raises(P.PlseError) as e:
+            P.plse_solve_batch([h1, h1], [10, 10], 8, 1, [1, 2], stream=0)
+        assert e.value.status == P.PLSE_E_ARG
+        with pytest.raises(P.PlseError) as e:
+            P.plse_solve_batch([h1, h2], [10, 10], 8, 1, [1, 2], stream=0)
+        assert e.value.status == P.PLSE_E_WORKSPACE
+        with pytest.raises(P.PlseError) as e:
+            P.plse_solve_batch([h1, h2], [10, 10], 8, 0, [1, 2], stream=0)
+        assert e.value.status == P.PLSE_E_ARG
+    finally:
+        P.plse_destroy(h1)
+        P.plse_destroy(h2)
+
+
+def test_server_argument_errors():
+    import ctypes
+    srv = ctypes.c_void_p()
+    L = P._lib()
+    assert L.plse_server_create(1 << 20, None, 4, None, ctypes.byref(srv)) == P.PLSE_E_ARG
+    assert L.plse_server_create(0, ctypes.c_void_p(4096), 4, None, ctypes.byref(srv)) == P.PLSE_E_ARG
+    assert L.plse_server_create(1 << 20, ctypes.c_void_p(4096), 0, None, ctypes.byref(srv)) == P.PLSE_E_ARG
+    assert L.plse_server_submit(None, None, 8, 1, 1, None) == P.PLSE_E_ARG
+    assert L.plse_server_destroy(None) == P.PLSE_E_ARG

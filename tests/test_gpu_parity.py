@@ -280,3 +280,119 @@ def test_full_size_n50_generation_sampled(torch_cuda, oracle_mod):
     # every output is a legal colouring within the domains
     Sfull = _np(S1)[:, :I.nv]
     assert Sfull.max() <= I.n
+
+
+# --- batched solve ---------------------------------------------------------------------
+def test_batch_equals_standalone_and_oracle(torch_cuda, oracle_mod):
+    """plse_solve_batch over instances of different orders returns, for each,
+    exactly what plse_solve returns alone and what the oracle computes."""
+    names = ["greedy20_50", "planted10", "greedy12_60", "planted33_45"]
+    grids = [_instances()[k] for k in names]
+    _say("batch of 4 mixed instances p=32 G=4")
+    p, G = 32, 4
+    seeds = [11 + 7 * i for i in range(len(grids))]
+    solvers = [P.Solver(g, depth=int(10 * g.shape[0] ** 2 // 4)) for g in grids]
+    res = P.Solver.solve_batch(solvers, p, G, seeds)
+    batch_stats = [s.stats() for s in solvers]
+    for i, g in enumerate(grids):
+        alone = P.Solver(g, depth=int(10 * g.shape[0] ** 2 // 4))
+        grid, filled = alone.solve(p, G, seeds[i])
+        assert filled == res[i][1]
+        np.testing.assert_array_equal(grid, res[i][0])
+        np.testing.assert_array_equal(alone.stats()["counters_per_gen"],
+                                      batch_stats[i]["counters_per_gen"])
+        I = oracle_mod.Instance(g)
+        r = I.run(I.params(depth=int(10 * g.shape[0] ** 2 // 4)), p, G, seeds[i])
+        assert r["filled"] == res[i][1]
+        np.testing.assert_array_equal(r["grid"], res[i][0])
+        np.testing.assert_array_equal(r["counters"], batch_stats[i]["counters_per_gen"])
+
+
+def test_batch_more_than_one_launch_chunk(torch_cuda, oracle_mod):
+    """More instances than one launch list holds (130 > 128), tiny sizes."""
+    _say("batch of 130 tiny instances p=8 G=2")
+    grids = [gen.random_greedy(4 + i % 5, 0.3 + 0.05 * (i % 5), 5000 + i) for i in range(130)]
+    solvers = [P.Solver(g, depth=60) for g in grids]
+    seeds = [900 + i for i in range(130)]
+    res = P.Solver.solve_batch(solvers, 8, 2, seeds)
+    for i in (0, 1, 63, 127, 128, 129):
+        I = oracle_mod.Instance(grids[i])
+        r = I.run(I.params(depth=60), 8, 2, seeds[i])
+        assert r["filled"] == res[i][1]
+        np.testing.assert_array_equal(r["grid"], res[i][0])
+
+
+# --- serving -------------------------------------------------------------------------------
+def _wait(srv, tickets, timeout_s=120.0):
+    import time
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout_s, "server did not finish in time"
+        time.sleep(0.002)
+    return out
+
+
+def test_served_results_equal_alone_and_in_mix(torch_cuda):
+    """Each request served alone and inside a mix of requests that arrive while
+    others run returns exactly what plse_solve returns (continuous batching)."""
+    import time
+    _say("serving: alone vs mix")
+    specs = [(gen.random_greedy(20, 0.5, 7), 24, 3, 1), (gen.planted(10, 0.4, 0), 16, 5, 2),
+             (gen.random_greedy(12, 0.6, 5), 24, 4, 3), (gen.planted(33, 0.45, 9), 16, 2, 4),
+             (gen.random_greedy(15, 0.4, 21), 24, 3, 5)]
+    want = []
+    for g, p, G, seed in specs:
+        s = P.Solver(g, depth=300)
+        want.append(s.solve(p, G, seed))
+    srv = P.Server(1 << 30, max_slots=3)
+    try:
+        # alone, one after the other
+        for i, (g, p, G, seed) in enumerate(specs):
+            t = srv.submit(P.Solver(g, depth=300), p, G, seed)
+            r = _wait(srv, [t])[t]
+            assert r["status"] == P.PLSE_OK and r["generations"] == G
+            assert r["filled"] == want[i][1]
+            np.testing.assert_array_equal(r["grid"], want[i][0])
+        # mixed: staggered arrivals, at most three resident at once
+        tickets = []
+        for i, (g, p, G, seed) in enumerate(specs):
+            tickets.append(srv.submit(P.Solver(g, depth=300), p, G, seed))
+            time.sleep(0.003 * i)
+        res = _wait(srv, tickets)
+        for i, t in enumerate(tickets):
+            assert res[t]["status"] == P.PLSE_OK
+            assert res[t]["filled"] == want[i][1]
+            np.testing.assert_array_equal(res[t]["grid"], want[i][0])
+            assert res[t]["admit_s"] >= res[t]["submit_s"] and res[t]["done_s"] >= res[t]["admit_s"]
+    finally:
+        srv.close()
+
+
+def test_server_capacity_and_fault_isolation(torch_cuda):
+    _say("serving: capacity refusal and fault hook")
+    small = P.Solver(gen.planted(10, 0.4, 0), depth=200)
+    big = P.Solver(gen.random_greedy(40, 0.3, 3), depth=200)
+    budget = small.ensure_workspace(16).numel() * 3
+    srv = P.Server(budget, max_slots=4)
+    try:
+        with pytest.raises(P.PlseError) as e:
+            srv.submit(big, 2048, 2, 1)
+        assert e.value.status == P.PLSE_E_CAPACITY
+        a = P.Solver(gen.planted(10, 0.4, 0), depth=200)
+        b = P.Solver(gen.planted(10, 0.4, 0), depth=200, fail_at_generation=2)
+        c = P.Solver(gen.random_greedy(12, 0.6, 5), depth=200)
+        ta, tb, tc = srv.submit(a, 16, 4, 7), srv.submit(b, 16, 4, 8), srv.submit(c, 16, 4, 9)
+        res = _wait(srv, [ta, tb, tc])
+        assert res[tb]["status"] == P.PLSE_E_FAULT and res[tb]["generations"] == 2
+        for solver, t, seed in ((a, ta, 7), (c, tc, 9)):
+            ref = P.Solver(solver.grid, depth=200).solve(16, 4, seed)
+            assert res[t]["status"] == P.PLSE_OK and res[t]["filled"] == ref[1]
+            np.testing.assert_array_equal(res[t]["grid"], ref[0])
+    finally:
+        srv.close()
