@@ -84,7 +84,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n50", choices=["n50", "n70_30", "n70_50", "n70_70",
-                                                         "small"])
+                                                         "small", "batch", "served"])
+    ap.add_argument("--instances", type=int, default=256, help="batch: number of instances")
+    ap.add_argument("--requests", type=int, default=16, help="served: number of requests")
+    ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
+    ap.add_argument("--generations", type=int, default=0,
+                    help="served: generations per request (default 50)")
     ap.add_argument("--lanes-per-vertex", type=int, default=0)
     ap.add_argument("--population", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,6 +118,10 @@ def main():
     from paper_2103_10453_amd import instances as gen
     from paper_2103_10453_amd import plse
 
+    if args.workload == "batch":
+        return bench_batch(args, gen, plse)
+    if args.workload == "served":
+        return bench_served(args, gen, plse)
     if args.workload == "n50":
         w = gen.workload_n50()
         desc = "planted n=50, 50% prefilled, population 16384, depth 10n^2 per generation"
@@ -183,6 +192,110 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w["grid"], w["seed"], w["depth"])
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, gen, plse):
+    """Many instances per launch (plse_solve_batch) vs one plse_solve per
+    instance, same seeds and generations: results must be identical."""
+    import numpy as np
+    import torch
+    torch.cuda.set_device(0)
+    work = gen.workload_batch(args.instances)
+    G = args.steps
+    solvers = [plse.Solver(w["grid"], depth=w["depth"]) for w in work]
+    p = work[0]["population"]
+    seeds = [w["seed"] for w in work]
+    for s in solvers:
+        s.ensure_workspace(p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res_b = plse.Solver.solve_batch(solvers, p, G, seeds)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    moves_b = sum(int(s.stats()["totals"][1]) for s in solvers)
+    t0 = time.perf_counter()
+    res_s = [s.solve(p, G, w["seed"]) for s, w in zip(solvers, work)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    moves_s = sum(int(s.stats()["totals"][1]) for s in solvers)
+    same = all(a[1] == b[1] and np.array_equal(a[0], b[0]) for a, b in zip(res_b, res_s))
+    print(json.dumps({
+        "metric": f"batched tabu moves/s ({len(work)} instances, pop {p}, {G} generations)",
+        "value": moves_b / t_batch, "unit": "moves/s", "n_gpus": 1, "steps": G, "warmup": 0,
+        "ms_per_step": t_batch / G * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch: n ~ U{20..70}, r ~ U[0.3, 0.7], half planted, half "
+                               "random-greedy, population 1024, depth 10n^2",
+                   "instances": len(work), "population": p},
+        "one_instance_per_launch": {"value": moves_s / t_seq, "seconds": t_seq},
+        "batched_seconds": t_batch, "speedup": t_seq / t_batch, "identical_results": same,
+        "filled_total": int(sum(r[1] for r in res_b))}), flush=True)
+
+
+def bench_served(args, gen, plse):
+    """Poisson request stream through the continuous-batching server vs the
+    same trace served one request at a time; same results required."""
+    import numpy as np
+    import torch
+    torch.cuda.set_device(0)
+    G = args.generations or 50
+    reqs = gen.workload_served(args.requests, args.rate)
+    for r in reqs:
+        r["generations"] = G
+    p = reqs[0]["population"]
+    budget = int(0.6 * torch.cuda.get_device_properties(0).total_memory)
+    # served: submit at arrival times, poll until all are done
+    srv = plse.Server(budget, max_slots=64)
+    solvers = [plse.Solver(r["grid"], depth=r["depth"]) for r in reqs]
+    tickets, results = [], {}
+    t0 = time.perf_counter()
+    i = 0
+    while len(results) < len(reqs):
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i]["arrival"] <= now:
+            tickets.append((i, srv.submit(solvers[i], p, G, reqs[i]["seed"])))
+            i += 1
+        for k, t in tickets:
+            if k not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[k] = r
+        time.sleep(0.001)
+    wall = time.perf_counter() - t0
+    srv.close()
+    del srv
+    lat = np.array([results[k]["done_s"] - results[k]["submit_s"] for k in range(len(reqs))])
+    ttb = np.array([results[k]["best_s"] - results[k]["submit_s"] for k in range(len(reqs))])
+    moves = sum(results[k]["moves"] for k in range(len(reqs)))
+    # baseline: the same arrivals, one plse_solve at a time in arrival order
+    base = []
+    t0 = time.perf_counter()
+    lat_b = []
+    for k, r in enumerate(reqs):
+        while time.perf_counter() - t0 < r["arrival"]:
+            time.sleep(0.0005)
+        s = plse.Solver(r["grid"], depth=r["depth"])
+        base.append(s.solve(p, G, r["seed"]))
+        lat_b.append(time.perf_counter() - t0 - r["arrival"])
+    wall_b = time.perf_counter() - t0
+    same = all(results[k]["filled"] == base[k][1] and np.array_equal(results[k]["grid"], base[k][0])
+               for k in range(len(reqs)))
+    pct = lambda a, q: float(np.percentile(a, q))
+    print(json.dumps({
+        "metric": f"served requests/s (Poisson {args.rate}/s, {len(reqs)} requests, pop {p}, "
+                  f"{G} generations)",
+        "value": len(reqs) / wall, "unit": "requests/s", "n_gpus": 1, "steps": G, "warmup": 0,
+        "ms_per_step": wall / G * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "served: n ~ U{10..100}, r ~ U[0.3, 0.7], planted or "
+                               "random-greedy, population 2048, depth 10n^2",
+                   "requests": len(reqs), "rate": args.rate, "generations": G},
+        "moves_per_s": moves / wall,
+        "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "time_to_best_s": {"p50": pct(ttb, 50), "p99": pct(ttb, 99)},
+        "one_at_a_time": {"requests_per_s": len(reqs) / wall_b,
+                          "latency_s": {"p50": pct(lat_b, 50), "p99": pct(lat_b, 99)}},
+        "identical_results": same}), flush=True)
 
 
 if __name__ == "__main__":
