@@ -12,6 +12,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -1196,6 +1197,7 @@ struct plse_server_s {
     std::deque<Request *> waiting;
     std::vector<Request *> resident;
     std::map<uint64_t, Request *> finished;
+    std::set<uint64_t> live;  // submitted and not yet finished (waiting, admitting, resident)
     std::map<size_t, size_t> free_blocks;  // offset -> bytes
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -1243,6 +1245,7 @@ struct plse_server_s {
         r->h->ws_bytes = 0;
         r->h->in_session = false;
         release(r);
+        live.erase(r->ticket);
         finished[r->ticket] = r;
     }
 
@@ -1379,6 +1382,7 @@ int plse_server_submit(plse_server s, plse_handle h, int32_t p, int32_t G, uint6
     r->ticket = s->next_ticket++;
     r->t_submit = s->now();
     *ticket = r->ticket;
+    s->live.insert(r->ticket);
     s->waiting.push_back(r);
     s->cv.notify_one();
     return PLSE_OK;
@@ -1391,13 +1395,7 @@ int plse_server_poll(plse_server s, uint64_t ticket, int8_t *best_grid, int32_t 
     {
         std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->finished.find(ticket);
-        if (it == s->finished.end()) {
-            for (Request *q : s->waiting)
-                if (q->ticket == ticket) return PLSE_PENDING;
-            for (Request *q : s->resident)
-                if (q->ticket == ticket) return PLSE_PENDING;
-            return PLSE_E_ARG;
-        }
+        if (it == s->finished.end()) return s->live.count(ticket) ? PLSE_PENDING : PLSE_E_ARG;
         r = it->second;
         s->finished.erase(it);
     }
