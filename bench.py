@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
     ap.add_argument("--generations", type=int, default=0,
                     help="served: generations per request (default 50)")
-    ap.add_argument("--lanes-per-vertex", type=int, default=0)
+    ap.add_argument("--slots-per-lane", type=int, default=0)
     ap.add_argument("--population", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
@@ -136,7 +136,7 @@ def main():
         w["population"] = args.population
     p = w["population"]
     torch.cuda.set_device(0)
-    s = plse.Solver(w["grid"], depth=w["depth"], lanes_per_vertex=args.lanes_per_vertex)
+    s = plse.Solver(w["grid"], depth=w["depth"], slots_per_lane=args.slots_per_lane)
     s.ensure_workspace(p)
     stream = torch.cuda.current_stream()
 
@@ -175,7 +175,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": int(w["grid"].shape[0]), "population": p,
                    "depth": int(w["depth"]),
-                   "lanes_per_vertex": int(s.get_param("lanes_per_vertex")),
+                   "slots_per_lane": int(s.get_param("slots_per_lane")),
                    "vertices": s.nv, "sum_domain": s.nd,
                    "waves_per_block": int(s.get_param("waves_per_block"))},
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",

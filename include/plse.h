@@ -93,8 +93,8 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *   "spacing"     minimum spacing factor gamma of Section 3.4 (10)
  *   "stop_at_ub"  1: stop after the generation whose best reaches the bound
  *   "nn_history"  partner-history length, 0..64 (64)
- *   "conf_bytes"  1 or 2: bytes per conflict-table entry (default 1; 2 is the
- *                 int16 table)
+ *   "slots_per_lane" 2, 4 or 8: candidate moves one lane evaluates per PLITS
+ *                 round (default 0: chosen from the domain sizes)
  *   "waves_per_block" 1, 2 or 4: PLITS launch shape (default: chosen from the
  *                 LDS footprint)
  * Errors: PLSE_E_PARAM.

@@ -55,8 +55,55 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     return h;
 }
 
+// Inverse of an odd 32-bit multiplier modulo 2^32 (Newton iteration, each
+// step doubling the number of correct low bits from the 3 that a * a = 1
+// (mod 8) gives).
+constexpr uint32_t inverse_odd(uint32_t a) {
+    uint32_t x = a;
+    for (int i = 0; i < 5; ++i) x *= 2u - a * x;
+    return x;
+}
+
+// fmix32^-1: undoes the finaliser step by step (x ^= x >> 13 is undone by
+// x ^= x >> 13 ^ x >> 26; x ^= x >> 16 is its own inverse).
+__device__ __forceinline__ uint32_t fmix32_inv(uint32_t h) {
+    constexpr uint32_t i2 = inverse_odd(0xC2B2AE35u), i1 = inverse_odd(0x85EBCA6Bu);
+    static_assert(i2 * 0xC2B2AE35u == 1u && i1 * 0x85EBCA6Bu == 1u, "modular inverse");
+    h ^= h >> 16;
+    h *= i2;
+    h ^= (h >> 13) ^ (h >> 26);
+    h *= i1;
+    h ^= h >> 16;
+    return h;
+}
+
 // floor(w * m / 2^32): uniform integer in [0, m).
 __device__ __forceinline__ uint32_t scale32(uint32_t w, uint32_t m) { return __umulhi(w, m); }
+
+// Global-memory views of generic pointers.  Accesses through them compile to
+// global_* instructions; flat_* accesses (what a pointer read from an argument
+// block would give) are also counted with the LDS operations, so that every
+// wait for an LDS result would wait for outstanding memory traffic too.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gptr(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+// 8- and 16-byte global accesses (clang vector types: HIP's uint2/uint4
+// classes only bind to generic-address references).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 gload4(const void *p) {
+    return *gptr(reinterpret_cast<const u32x4 *>(p));
+}
+__device__ __forceinline__ u32x2 gload2(const void *p) {
+    return *gptr(reinterpret_cast<const u32x2 *>(p));
+}
+__device__ __forceinline__ void gstore4(void *p, u32x4 v) { *gptr(reinterpret_cast<u32x4 *>(p)) = v; }
 
 // ---------------------------------------------------------------------------
 // wave64 collectives.  All lanes of the wave must be active at the call.

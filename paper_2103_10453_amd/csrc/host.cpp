@@ -44,7 +44,7 @@ int colour_bits(int n) {
 
 // Offsets of every device array of one handle, for a population p.
 struct Layout {
-    size_t vrc, vrec, dom, rowl, coll, rowc, colc;
+    size_t vrc, vrec, cand, vinfo, rowl, coll, rowc, colc;
     size_t args, ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
     size_t tabu, planes, D, deg, adj, keys, rej, acc, hkeys, hvals, partner, dpart;
@@ -76,17 +76,19 @@ struct Session;
 
 struct plse_instance {
     int n = 0, nv = 0, l = 0, ub = 0, nd = 0, stride = 16;
+    int dmax = 0, ts = 8;  // largest |D*(v)|; candidate row length (dmax + 1 rounded to 8)
     std::vector<int8_t> grid;
     std::vector<int> cell_v;  // -1 prefilled, -2 impossible, else vertex id
     // host images of the device instance tables
     std::vector<uint16_t> vrc;
     std::vector<uint32_t> vrec;  // 8 words per vertex
-    std::vector<uint8_t> dom;    // domain colour lists
+    std::vector<uint8_t> cand;   // [nv][ts] candidate rows: 0, D*(v) ascending, 0 padding
+    std::vector<uint32_t> vinfo; // [nv] row | column << 8 | |D*(v)| << 16
     std::vector<uint32_t> rowl, coll;
     std::vector<uint8_t> rowc, colc;
 
     Params P{};
-    int lpv = 0;  // lanes per eligible vertex in PLITS; 0: automatic
+    int spl = 0;  // candidate positions per lane and round in PLITS; 0: automatic
     int wpb = 0;  // waves per block in PLITS; 0: automatic
     int fail_at = 0;  // serving test hook: end the request after this generation
 
@@ -151,20 +153,44 @@ void set_attributes_once() {
 
 int max_lds_per_block() { return g_lds_limit; }
 
+// Candidate positions per lane and round in PLITS: the chunk size CH that
+// minimises the modelled evaluation work of one pass over every candidate
+// row, sum_v ceil((d_v + 1) / CH) (CH + 1.5), the 1.5 standing for a chunk's
+// fixed work (descriptor, vertex state, loads) in units of one move.
+int choose_spl(const plse_instance *h) {
+    if (h->spl) return h->spl;
+    int pick = 4;
+    double best = 0.0;
+    for (int ch : {2, 4, 8}) {
+        double cost = 0.0;
+        for (int v = 0; v < h->nv; ++v) cost += (double)(((h->vinfo[v] >> 16) + ch) / ch) * (ch + 1.5);
+        if (ch == 2 || cost < best) {
+            best = cost;
+            pick = ch;
+        }
+    }
+    return pick;
+}
+
 // PLITS per-wave LDS: S, row/column colour counts, eligibility bitmap,
-// per-vertex tabu expiry, eligible-vertex list.
+// per-vertex tabu expiry (u16), eligible-vertex list, ring of chunk
+// descriptors (one group of 64 vertices dealt while under 64 are pending).
 struct PlitsLds {
-    int per_wave, off_h, off_bm, off_tm, off_el;
+    int per_wave, off_h, off_bm, off_tm, off_el, off_ring, qmask;
 };
 
 PlitsLds plits_lds(const plse_instance *h) {
     PlitsLds L;
     const int W = (h->nv + 31) / 32;
+    const int ch = choose_spl(h);
+    const int qcap = next_pow2(63 + 64 * ((h->dmax + ch) / ch));
     L.off_h = h->stride;
     L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
     L.off_tm = L.off_bm + (int)round_up((size_t)W * 4, 16);
-    L.off_el = L.off_tm + (int)round_up((size_t)h->nv * 4, 16);
-    L.per_wave = L.off_el + (int)round_up((size_t)h->nv * 2, 16);
+    L.off_el = L.off_tm + (int)round_up((size_t)h->nv * 2, 16);
+    L.off_ring = L.off_el + (int)round_up((size_t)h->nv * 2, 16);
+    L.per_wave = L.off_ring + qcap * 4;
+    L.qmask = qcap - 1;
     return L;
 }
 
@@ -187,16 +213,6 @@ int choose_wpb(const plse_instance *h) {
     return h->wpb ? h->wpb : auto_wpb(plits_lds(h).per_wave);
 }
 
-// Lanes per eligible vertex: about four domain colours per lane.
-int choose_lpv(const plse_instance *h) {
-    if (h->lpv) return h->lpv;
-    const double mean = h->nv ? (double)h->nd / h->nv : 1.0;
-    if (mean <= 6.0) return 1;
-    if (mean <= 12.0) return 2;
-    if (mean <= 24.0) return 4;
-    return 8;
-}
-
 Layout plan(const plse_instance *h, int p) {
     Layout L{};
     size_t o = 0;
@@ -210,7 +226,8 @@ Layout plan(const plse_instance *h, int p) {
     const int W = (h->nv + 31) / 32, B = colour_bits(h->n);
     L.vrc = take(2 * nv);
     L.vrec = take(32 * nv);
-    L.dom = take(nd + 16);
+    L.cand = take(nv * (size_t)h->ts);
+    L.vinfo = take(4 * nv);
     L.rowl = take(4 * n * n);
     L.coll = take(4 * n * n);
     L.rowc = take(n);
@@ -231,7 +248,7 @@ Layout plan(const plse_instance *h, int p) {
     L.hc = take(4 * (size_t)p);
     L.hc_tmp = take(4 * (size_t)p);
     L.cnt = take(8 * (size_t)p * kCounters);
-    L.tabu = take((size_t)p * (nd + nv) * 4);
+    L.tabu = take((size_t)p * nv * h->ts * 4);
     L.planes = take(m * W * B * 4);
     L.D = take(m * m * 2);
     L.deg = take(4 * m);
@@ -260,12 +277,14 @@ DevInstance dev_instance(plse_instance *h) {
     I.n = h->n;
     I.nv = h->nv;
     I.nd = h->nd;
+    I.ts = h->ts;
     I.stride = h->stride;
     I.l = h->l;
     I.ub = h->ub;
     I.vrc = at<uint16_t>(h, L.vrc);
     I.vrec = at<void>(h, L.vrec);
-    I.dom = at<uint8_t>(h, L.dom);
+    I.cand = at<uint8_t>(h, L.cand);
+    I.vinfo = at<uint32_t>(h, L.vinfo);
     I.rowl = at<uint32_t>(h, L.rowl);
     I.coll = at<uint32_t>(h, L.coll);
     I.rowc = at<uint8_t>(h, L.rowc);
@@ -281,7 +300,8 @@ int upload_instance(plse_instance *h, hipStream_t s) {
     };
     HIP_TRY(put(L.vrc, h->vrc.data(), 2 * h->vrc.size()));
     HIP_TRY(put(L.vrec, h->vrec.data(), 4 * h->vrec.size()));
-    HIP_TRY(put(L.dom, h->dom.data(), h->dom.size()));
+    HIP_TRY(put(L.cand, h->cand.data(), h->cand.size()));
+    HIP_TRY(put(L.vinfo, h->vinfo.data(), 4 * h->vinfo.size()));
     HIP_TRY(put(L.rowl, h->rowl.data(), 4 * h->rowl.size()));
     HIP_TRY(put(L.coll, h->coll.data(), 4 * h->coll.size()));
     HIP_TRY(put(L.rowc, h->rowc.data(), h->rowc.size()));
@@ -325,6 +345,8 @@ PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
     a.off_bm = pl.off_bm;
     a.off_tm = pl.off_tm;
     a.off_el = pl.off_el;
+    a.off_ring = pl.off_ring;
+    a.qmask = pl.qmask;
     return a;
 }
 
@@ -371,7 +393,7 @@ void build_pipeline_args(plse_instance *h, int p, uint64_t seed) {
     A.init = InitArgs{dev_instance(h), S_all, f_all, p, next_pow2(std::max(4, h->nv)), slo, shi};
     A.pop = PopSetupArgs{p, st, at<uint64_t>(h, L.uid), at<int32_t>(h, L.hc), S_all,
                          at<uint8_t>(h, L.S_off)};
-    A.fill = FillArgs{at<uint32_t>(h, L.tabu), (size_t)p * (h->nd + h->nv)};
+    A.fill = FillArgs{at<uint32_t>(h, L.tabu), (size_t)p * h->nv * h->ts};
     A.plits = make_plits(h, p, 0, seed, at<uint8_t>(h, L.S_off), S_new, f_all + p,
                          at<uint64_t>(h, L.cnt), ctl);
     A.best = BestArgs{ctl, at<GenStat>(h, L.stats), f_all + p, S_new, at<uint64_t>(h, L.cnt),
@@ -443,13 +465,13 @@ struct Session {
 
 int enqueue_local_search(Session &S, hipStream_t s) {
     RC_TRY(launch_ctl(S.hs, false, s));
-    for (int lpv : {1, 2, 4, 8}) {
+    for (int spl : {2, 4, 8}) {
         std::vector<plse_instance *> g;
         for (plse_instance *h : S.hs)
-            if (choose_lpv(h) == lpv) g.push_back(h);
+            if (choose_spl(h) == spl) g.push_back(h);
         if (g.empty()) continue;
         RC_TRY(launch_over(g, &ArgBlock::plits, [&](const ArgList &L, int c) {
-            return launch_plits(L, c, S.p, S.lds_per_wave, lpv, S.wpb, s);
+            return launch_plits(L, c, S.p, S.lds_per_wave, spl, S.wpb, s);
         }));
     }
     return PLSE_OK;
@@ -743,8 +765,10 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
         }
     h->ub = (h->l == 1) ? n * n - 2 : n * n - h->l;
     // vertex records: 128-bit domain mask, first slot (sum of earlier domain
-    // sizes), coordinates and domain size; domain colour lists
+    // sizes), coordinates and domain size; vertex info words; candidate rows
+    // (the moves 0, D*(v) ascending, zero padded to ts positions)
     h->vrec.assign((size_t)h->nv * 8, 0);
+    h->vinfo.assign(h->nv, 0);
     uint32_t off = 0;
     for (int v = 0; v < h->nv; ++v) {
         uint32_t *r = &h->vrec[(size_t)v * 8];
@@ -756,11 +780,19 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
                                       __builtin_popcountll(dmask[2 * v + 1]));
         r[4] = off;
         r[5] = (uint32_t)h->vrc[v] | (d << 16);
-        for (int k = 1; k <= n; ++k)
-            if ((dmask[2 * v + (k >> 6)] >> (k & 63)) & 1ull) h->dom.push_back((uint8_t)k);
+        h->vinfo[v] = (uint32_t)h->vrc[v] | (d << 16);
+        h->dmax = std::max(h->dmax, (int)d);
         off += d;
     }
     h->nd = (int)off;
+    h->ts = (int)round_up((size_t)h->dmax + 1, 8);
+    h->cand.assign((size_t)h->nv * h->ts, 0);
+    for (int v = 0; v < h->nv; ++v) {
+        uint8_t *row = &h->cand[(size_t)v * h->ts];
+        int t = 1;
+        for (int k = 1; k <= n; ++k)
+            if ((dmask[2 * v + (k >> 6)] >> (k & 63)) & 1ull) row[t++] = (uint8_t)k;
+    }
     h->stride = (int)round_up((size_t)std::max(h->nv, 1), 16);
     // defaults: Table 1 and Section 3.3, total depth 10 n^2
     const int64_t depth = 10LL * n * n;
@@ -837,9 +869,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "nn_history") {
         if (v < 0 || v > kHist) return PLSE_E_PARAM;
         P.hist_len = (int32_t)v;
-    } else if (k == "lanes_per_vertex") {
-        if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return PLSE_E_PARAM;
-        h->lpv = (int)v;
+    } else if (k == "slots_per_lane") {
+        if (v != 0 && v != 2 && v != 4 && v != 8) return PLSE_E_PARAM;
+        h->spl = (int)v;
     } else if (k == "waves_per_block") {
         if (v != 0 && v != 1 && v != 2 && v != 4) return PLSE_E_PARAM;
         h->wpb = (int)v;
@@ -866,7 +898,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "spacing") *v = P.spacing;
     else if (k == "stop_at_ub") *v = P.stop_at_ub;
     else if (k == "nn_history") *v = P.hist_len;
-    else if (k == "lanes_per_vertex") *v = choose_lpv(h);
+    else if (k == "slots_per_lane") *v = choose_spl(h);
     else if (k == "waves_per_block") *v = choose_wpb(h);
     else if (k == "fail_at_generation") *v = h->fail_at;
     else return PLSE_E_PARAM;
@@ -1040,13 +1072,13 @@ int plse_stage_plits(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     RC_TRY(stage_prepare(h, p, s));
     h->args.plits = make_plits(h, p, gen, seed, S_in, S_out, f_out, counters, nullptr);
-    h->args.fill = FillArgs{at<uint32_t>(h, h->L.tabu), (size_t)p * (h->nd + h->nv)};
+    h->args.fill = FillArgs{at<uint32_t>(h, h->L.tabu), (size_t)p * h->nv * h->ts};
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_fill_zero(single(h, &ArgBlock::fill), 1, s));
     const int wpb = choose_wpb(h);
     if (wpb * plits_lds(h).per_wave > max_lds_per_block()) return PLSE_E_ARG;
     HIP_TRY(launch_plits(single(h, &ArgBlock::plits), 1, p, plits_lds(h).per_wave,
-                         choose_lpv(h), wpb, s));
+                         choose_spl(h), wpb, s));
     return PLSE_OK;
 }
 

@@ -10,20 +10,30 @@
 // column.  These 2 n (n+1) byte counters replace the sum_v |D*(v)| table, live
 // in LDS, and a move updates four of them instead of every neighbour's entry.
 //
+// Candidate rows.  The moves of vertex v are the colours of {0} u D*(v)
+// (0: uncolour), kept ascending at cand[v][0 .. d] with d = |D*(v)|, TS
+// positions per vertex; the tabu expiry of each move sits at the same
+// position of tabu[v].  An iteration cuts the rows of its eligible vertices
+// into chunks of CH consecutive positions and deals the chunks to the 64
+// lanes round by round, so every lane evaluates CH moves per round whatever
+// the domain sizes are.
+//
 // Per wave (LDS): S[stride] colours, rowcnt|colcnt, the eligibility bitmap of
-//   V_0 u C(S), tmax[|V|] (latest tabu expiry written per vertex: a vertex
-//   whose tmax is not above the iteration has no tabu move), and the list of
-//   eligible vertices of the iteration.
-// Per individual (HBM): tabu[nd + nv] "allowed from" iteration of every
-//   (v, k in D(v)), read only for vertices with a live entry; all zero between
-//   phases (each phase clears the rows it wrote).
+//   V_0 u C(S), tmax[|V|] (latest tabu expiry written per vertex, saturating
+//   at 0xFFFF: a vertex whose tmax is not above the iteration has no tabu
+//   move), the list of eligible vertices of the iteration and a ring of
+//   chunk descriptors.
+// Per individual (HBM): tabu[|V|][TS] "allowed from" iteration of every move,
+//   read only for vertices with a live entry; all zero between phases (each
+//   phase clears the rows it wrote).
 //
 // One iteration:
 //   1. eligible vertices V_0 u C(S) from the bitmap (wave prefix sum);
-//   2. LPV lanes per eligible vertex evaluate interleaved slots of its domain,
-//      eight at a time: move value from the row/column counts, admissibility
-//      from tabu and aspiration, best (value, tie-hash) key per lane;
-//   3. DPP wave minimum picks the unique best admissible move;
+//   2. chunks of their candidate rows, CH moves per lane and round: move value
+//      from the row/column counts, admissibility from tabu and aspiration,
+//      best (value, tie-hash) key per lane;
+//   3. DPP wave minimum picks the unique best admissible move; the tie hash
+//      is a bijection of the move id, so the key alone names the move;
 //   4. counts, colour, eligibility bits of the row/column vertices holding the
 //      old or new colour, tenure, tabu entry, best-solution snapshot.
 #include "device_common.h"
@@ -37,8 +47,9 @@ struct WaveState {
     uint8_t *S;
     uint8_t *H;        // rowcnt [n][n+1] then colcnt [n][n+1]
     uint32_t *bm;
-    uint32_t *tmax;
+    uint16_t *tmax;
     uint16_t *elist;
+    uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16
 };
 
 struct Scal {
@@ -47,31 +58,15 @@ struct Scal {
     int32_t fbest, cbest;
 };
 
-// 128-bit domain mask, first slot offset, coordinates and domain size of a
-// vertex.
-struct VRec {
-    uint64_t m0, m1;
-    uint32_t doff;
-    int r, c, d;
-};
-
-__device__ __forceinline__ VRec load_rec(const DevInstance &I, int v) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(I.vrec) + 2 * v;
-    const uint4 a = p[0], b = p[1];
-    VRec R;
-    R.m0 = ((uint64_t)a.y << 32) | a.x;
-    R.m1 = ((uint64_t)a.w << 32) | a.z;
-    R.doff = b.x;
-    R.r = (int)(b.y & 0xFFu);
-    R.c = (int)((b.y >> 8) & 0xFFu);
-    R.d = (int)(b.y >> 16);
-    return R;
-}
-
-// Slot of colour k in D*(v): number of domain colours below k.
-__device__ __forceinline__ uint32_t slot_of(const VRec &R, int k) {
-    if (k < 64) return (uint32_t)__popcll(R.m0 & ((1ull << k) - 1ull));
-    return (uint32_t)__popcll(R.m0) + (uint32_t)__popcll(R.m1 & ((1ull << (k - 64)) - 1ull));
+// Position of colour k in the candidate row of v: 0 for k = 0, else 1 + the
+// number of domain colours below k (from the vertex's 128-bit domain mask).
+__device__ __forceinline__ uint32_t position_of(const DevInstance &I, int v, int k) {
+    if (k == 0) return 0u;
+    const u32x4 a = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
+    const uint64_t m0 = ((uint64_t)a.y << 32) | a.x;
+    const uint64_t m1 = ((uint64_t)a.w << 32) | a.z;
+    if (k < 64) return 1u + (uint32_t)__popcll(m0 & ((1ull << k) - 1ull));
+    return 1u + (uint32_t)__popcll(m0) + (uint32_t)__popcll(m1 & ((1ull << (k - 64)) - 1ull));
 }
 
 // S from `src`; row/column colour counts; eligibility bitmap; f, c, |C(S)|.
@@ -80,7 +75,7 @@ __device__ void setup_state(const DevInstance &I, const uint8_t *src, const Wave
     const int lane = lane_id();
     const int n = I.n, nv = I.nv, np1 = n + 1;
     for (int q = lane; q < (I.stride >> 4); q += 64)
-        reinterpret_cast<uint4 *>(ws.S)[q] = reinterpret_cast<const uint4 *>(src)[q];
+        reinterpret_cast<u32x4 *>(ws.S)[q] = gload4(reinterpret_cast<const u32x4 *>(src) + q);
     const int hbytes = 2 * n * np1;
     uint32_t *h32 = reinterpret_cast<uint32_t *>(ws.H);
     for (int q = lane; q < (hbytes + 3) / 4; q += 64) h32[q] = 0u;
@@ -88,7 +83,7 @@ __device__ void setup_state(const DevInstance &I, const uint8_t *src, const Wave
     for (int v = lane; v < nv; v += 64) {
         const int s = ws.S[v];
         if (s) {
-            const uint32_t rc = I.vrc[v];
+            const uint32_t rc = gptr(I.vrc)[v];
             const int a = (int)(rc & 0xFFu) * np1 + s;
             const int b = n * np1 + (int)(rc >> 8) * np1 + s;
             atomicAdd(&h32[a >> 2], 1u << ((a & 3) * 8));
@@ -106,7 +101,7 @@ __device__ void setup_state(const DevInstance &I, const uint8_t *src, const Wave
             const int s = ws.S[v];
             int own = 0;
             if (s) {
-                const uint32_t rc = I.vrc[v];
+                const uint32_t rc = gptr(I.vrc)[v];
                 own = (int)rowH[(rc & 0xFFu) * np1 + s] + (int)colH[(rc >> 8) * np1 + s] - 2;
             }
             if (s == 0 || own > 0) bits |= 1u << (v & 31);
@@ -116,7 +111,7 @@ __device__ void setup_state(const DevInstance &I, const uint8_t *src, const Wave
         }
         ws.bm[w] = bits;
     }
-    for (int v = lane; v < nv; v += 64) ws.tmax[v] = 0u;
+    for (int v = lane; v < nv; v += 64) ws.tmax[v] = 0;
     PLSE_WAVE_SYNC();
     sc.f = (int32_t)wave_sum_u32_dpp(f);
     sc.c = (int32_t)(wave_sum_u32_dpp(c2) >> 1);  // each conflicting edge seen twice
@@ -125,31 +120,81 @@ __device__ void setup_state(const DevInstance &I, const uint8_t *src, const Wave
 
 __device__ __forceinline__ void snapshot(const DevInstance &I, const uint8_t *S, uint8_t *dst) {
     for (int q = lane_id(); q < (I.stride >> 4); q += 64)
-        reinterpret_cast<uint4 *>(dst)[q] = reinterpret_cast<const uint4 *>(S)[q];
+        gstore4(reinterpret_cast<u32x4 *>(dst) + q, reinterpret_cast<const u32x4 *>(S)[q]);
 }
 
 // Zero the tabu rows this phase wrote (their vertices have tmax > 0).
 __device__ void clear_tabu(const DevInstance &I, uint32_t *tabu, const WaveState &ws) {
+    const int q4 = I.ts >> 2;
     for (int v = lane_id(); v < I.nv; v += 64) {
         if (ws.tmax[v]) {
-            const VRec R = load_rec(I, v);
-            uint32_t *tb = tabu + R.doff + v;
-            for (int t = 0; t <= R.d; ++t) tb[t] = 0u;
+            u32x4 *tb = reinterpret_cast<u32x4 *>(tabu + (size_t)v * I.ts);
+            for (int t = 0; t < q4; ++t) gstore4(tb + t, u32x4{0u, 0u, 0u, 0u});
         }
     }
 }
 
-template <int LPV>
+// CH consecutive candidate colours (bytes) and their tabu expiries.
+template <int CH>
+struct Chunk;
+
+template <>
+struct Chunk<2> {
+    static __device__ __forceinline__ uint32_t colours(const uint8_t *p) {
+        return *gptr(reinterpret_cast<const uint16_t *>(p));
+    }
+    static __device__ __forceinline__ void tabu(const uint32_t *p, uint32_t *t) {
+        const u32x2 a = gload2(p);
+        t[0] = a.x;
+        t[1] = a.y;
+    }
+};
+
+template <>
+struct Chunk<4> {
+    static __device__ __forceinline__ uint32_t colours(const uint8_t *p) {
+        return *gptr(reinterpret_cast<const uint32_t *>(p));
+    }
+    static __device__ __forceinline__ void tabu(const uint32_t *p, uint32_t *t) {
+        const u32x4 a = gload4(p);
+        t[0] = a.x;
+        t[1] = a.y;
+        t[2] = a.z;
+        t[3] = a.w;
+    }
+};
+
+template <>
+struct Chunk<8> {
+    static __device__ __forceinline__ uint64_t colours(const uint8_t *p) {
+        return *gptr(reinterpret_cast<const uint64_t *>(p));
+    }
+    static __device__ __forceinline__ void tabu(const uint32_t *p, uint32_t *t) {
+        const u32x4 a = gload4(p);
+        const u32x4 b = gload4(p + 4);
+        t[0] = a.x;
+        t[1] = a.y;
+        t[2] = a.z;
+        t[3] = a.w;
+        t[4] = b.x;
+        t[5] = b.y;
+        t[6] = b.z;
+        t[7] = b.w;
+    }
+};
+
+template <int CH>
 __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t slot,
                           uint32_t gen, const uint8_t *src, uint8_t *out, uint32_t *tabu,
                           const WaveState &ws, Scal &sc, uint64_t *ucnt, uint32_t &lane_cands) {
     const DevInstance &I = a.I;
     const int lane = lane_id();
-    const int n = I.n, nv = I.nv, np1 = n + 1;
+    const int n = I.n, nv = I.nv, np1 = n + 1, TS = I.ts;
     // F = phi_den f + phi_num c: phase 1 phi = 1/2, phase 2 phi = |V|.
     const int32_t phi_num = (phase == 1) ? 1 : nv;
     const int32_t phi_den = (phase == 1) ? 2 : 1;
     const uint32_t tag = (phase == 1) ? TAG_PLITS1 : TAG_PLITS2;
+    const uint32_t qmask = (uint32_t)a.qmask;
     uint8_t *rowH = ws.H;
     uint8_t *colH = ws.H + n * np1;
 
@@ -160,11 +205,16 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     sc.fbest = sc.f;
     sc.cbest = sc.c;
     const int W = (nv + 31) >> 5;
-    const int grp = lane / LPV, q = lane % LPV;
-    constexpr int VPP = 64 / LPV;  // vertices per evaluation pass
+    uint32_t wx = 0u, wy = 0u;  // random words of iterations (it & ~63) + lane
     PLSE_WAVE_SYNC();
 
     for (int64_t it = 0; it < iters; ++it) {
+        const uint32_t itu = (uint32_t)it;
+        if ((itu & 63u) == 0u) {
+            const U4 rw = draw(a.seed_lo, a.seed_hi, slot, gen, tag, itu + (uint32_t)lane);
+            wx = rw.x;
+            wy = rw.y;
+        }
         // 1. eligible vertices, ascending
         uint32_t m = 0;
         for (int wb = 0; wb < W; wb += 64) {
@@ -183,68 +233,82 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         PLSE_WAVE_SYNC();
         ucnt[C_ITERS]++;
         ucnt[C_ELIG] += m;
-        const U4 rw = draw(a.seed_lo, a.seed_hi, slot, gen, tag, (uint32_t)it);
-        const uint32_t itu = (uint32_t)it;
+        const uint32_t w0 = readlane_u32(wx, (int)(itu & 63u));
+        const uint32_t w1 = readlane_u32(wy, (int)(itu & 63u));
 
-        // 2. best admissible one-move per lane.  Lane q of a vertex's group
-        //    takes domain slots q, q + LPV, ...; eight slots per batch: the
-        //    colour and tabu loads of a batch are issued together, then its
-        //    row/column count reads, then branch-free key selection.
+        // 2. best admissible one-move per lane over the chunk rounds.
         //    Aspiration F + delta < F* is delta < thr (F* - F clamped to int32).
         const int64_t gap = sc.Fbest - sc.F;
         const int32_t thr = gap < (int64_t)INT32_MIN ? INT32_MIN : (int32_t)gap;
         uint64_t lbest = ~0ull;
         uint32_t lpay = 0u;
-        for (uint32_t e = (uint32_t)grp; e < m; e += VPP) {
-            const int v = ws.elist[e];
-            const VRec R = load_rec(I, v);
-            const int s = ws.S[v];
-            const uint8_t *rH = rowH + R.r * np1;
-            const uint8_t *cH = colH + R.c * np1;
-            const int32_t cur = s ? ((int32_t)rH[s] + (int32_t)cH[s] - 2) : 0;
-            const bool live = ws.tmax[v] > itu;
-            const uint32_t *tb = tabu + R.doff + v;  // [0] colour 0, [1 + j] slot j
-            const uint8_t *dl = I.dom + R.doff;      // colours of D*(v), ascending
-            const int d = R.d;
-            if (q == 0) lane_cands += (uint32_t)d;
-            const int32_t dfb = s ? 0 : -phi_den;
-            const uint32_t cid0 = (uint32_t)(v * np1);
-            for (int jb = q; jb < d; jb += 8 * LPV) {
-                int kk[8];
-                uint32_t tv[8];
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int j = jb + t * LPV;
-                    kk[t] = (j < d) ? (int)dl[j] : 0;
-                    tv[t] = (live && j < d) ? tb[1 + j] : 0u;
+        uint32_t head = 0u, tail = 0u, g = 0u;
+        for (;;) {
+            // deal the rows of the next 64 eligible vertices while fewer than
+            // a round of chunks is pending
+            while (tail - head < 64u && g < m) {
+                const uint32_t e = g + (uint32_t)lane;
+                uint32_t v = 0u, nch = 0u;
+                if (e < m) {
+                    v = ws.elist[e];
+                    const uint32_t d = gptr(I.vinfo)[v] >> 16;
+                    nch = (d + CH) / CH;  // d + 1 positions
+                    lane_cands += d;
                 }
-                int cnt[8];
+                uint32_t total;
+                const uint32_t at = tail + wave_excl_scan_dpp(nch, &total);
+                for (uint32_t t = 0; t < nch; ++t) ws.ring[(at + t) & qmask] = v | (t << 16);
+                tail += total;
+                g += 64u;
+                PLSE_WAVE_SYNC();
+            }
+            if (head == tail) break;
+            const uint32_t x = head + (uint32_t)lane;
+            head = min(head + 64u, tail);
+            if (x < tail) {
+                const uint32_t ent = ws.ring[x & qmask];
+                const int v = (int)(ent & 0xFFFFu);
+                const int p0 = (int)(ent >> 16) * CH;
+                const int s = ws.S[v];
+                const uint32_t tm = ws.tmax[v];
+                const bool live = tm > itu || tm == 0xFFFFu;
+                const uint32_t vi = gptr(I.vinfo)[v];
+                const auto cw = Chunk<CH>::colours(I.cand + (size_t)v * TS + p0);
+                uint32_t tv[CH];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) cnt[t] = (int)rH[kk[t]] + (int)cH[kk[t]];
+                for (int t = 0; t < CH; ++t) tv[t] = 0u;
+                if (live) Chunk<CH>::tabu(tabu + (size_t)v * TS + p0, tv);
+                const int r = (int)(vi & 0xFFu), c = (int)((vi >> 8) & 0xFFu);
+                const int lim = (int)(vi >> 16) - p0;  // positions t <= lim exist
+                const uint8_t *rH = rowH + r * np1;
+                const uint8_t *cH = colH + c * np1;
+                const int32_t cur = s ? ((int32_t)rH[s] + (int32_t)cH[s] - 2) : 0;
+                // delta = phi_den df + phi_num (conf(v,k) - cur), df = -1 when v
+                // was uncoloured, +1 for the uncolour move (k = 0, position 0)
+                const int32_t base = (s ? 0 : -phi_den) - phi_num * cur;
+                const uint32_t cid0 = (uint32_t)v * (uint32_t)np1;
+                const uint32_t vpay = (uint32_t)v | ((uint32_t)r << 14) | ((uint32_t)c << 21);
+                int kk[CH], cnt[CH];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int j = jb + t * LPV;
+                for (int t = 0; t < CH; ++t) kk[t] = (int)((cw >> (8 * t)) & 0xFFu);
+#pragma unroll
+                for (int t = 0; t < CH; ++t) cnt[t] = (int)rH[kk[t]] + (int)cH[kk[t]];
+#pragma unroll
+                for (int t = 0; t < CH; ++t) {
                     const int k = kk[t];
-                    const int32_t delta = dfb + phi_num * (cnt[t] - cur);
-                    const bool ok = (j < d) && (k != s) && (itu >= tv[t] || delta < thr);
+                    const int32_t b = (t == 0 && p0 == 0) ? base + phi_den : base;
+                    const int32_t delta = phi_num * cnt[t] + b;
+                    const bool ok = (t <= lim) && (k != s) && (itu >= tv[t] || delta < thr);
                     const uint64_t key = ((uint64_t)((uint32_t)delta + 0x80000000u) << 32) |
-                                         fmix32(rw.y ^ (cid0 + (uint32_t)k));
+                                         fmix32(w1 ^ (cid0 + (uint32_t)k));
                     const bool take = ok && key < lbest;
                     lbest = take ? key : lbest;
-                    lpay = take ? (((uint32_t)v << 8) | (uint32_t)k) : lpay;
+                    lpay = take ? vpay : lpay;
                 }
             }
-            if (s && q == 0) {  // a conflicting vertex may also become uncoloured
-                const int32_t delta = phi_den - phi_num * cur;
-                const uint32_t t0 = live ? tb[0] : 0u;
-                const uint64_t key =
-                    ((uint64_t)((uint32_t)delta + 0x80000000u) << 32) | fmix32(rw.y ^ cid0);
-                const bool take = (itu >= t0 || delta < thr) && key < lbest;
-                lbest = take ? key : lbest;
-                lpay = take ? ((uint32_t)v << 8) : lpay;
-            }
+            PLSE_WAVE_SYNC();
         }
-        // 3. unique best over the wave
+        // 3. unique best over the wave; the low key word inverts to the move id
         const uint64_t gmin = wave_min_u64_dpp(lbest);
         if (gmin == ~0ull) {
             ucnt[C_IDLE]++;
@@ -252,13 +316,15 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         }
         const uint64_t who = ballot(lbest == gmin);
         const uint32_t pay = readlane_u32(lpay, (int)__ffsll((unsigned long long)who) - 1);
-        const int v = (int)(pay >> 8);
-        const int k = (int)(pay & 0xFFu);
+        const int v = (int)(pay & 0x3FFFu);
+        const int r = (int)((pay >> 14) & 0x7Fu);
+        const int c = (int)((pay >> 21) & 0x7Fu);
+        const uint32_t cid = fmix32_inv((uint32_t)gmin) ^ w1;
+        const int k = (int)(cid - (uint32_t)v * (uint32_t)np1);
         const int32_t delta = (int32_t)((uint32_t)(gmin >> 32) - 0x80000000u);
-        const VRec R = load_rec(I, v);
         const int old = ws.S[v];
-        uint8_t *rH = rowH + R.r * np1;
-        uint8_t *cH = colH + R.c * np1;
+        uint8_t *rH = rowH + r * np1;
+        uint8_t *cH = colH + c * np1;
         const int32_t cvk = k ? ((int32_t)rH[k] + (int32_t)cH[k]) : 0;
         const int32_t cvo = old ? ((int32_t)rH[old] + (int32_t)cH[old] - 2) : 0;
         PLSE_WAVE_SYNC();
@@ -276,14 +342,15 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         }
         PLSE_WAVE_SYNC();
         // eligibility of the row/column vertices holding the old or new colour
-        const int nr = I.rowc[R.r], nc = I.colc[R.c];
+        const int nr = gptr(I.rowc)[r], nc = gptr(I.colc)[c];
         int32_t dC = 0;
         for (int t0 = 0; t0 < nr + nc; t0 += 64) {
             const int t = t0 + lane;
             bool enter = false, leave = false;
             if (t < nr + nc) {
                 const bool inrow = t < nr;
-                const uint32_t ent = inrow ? I.rowl[R.r * n + t] : I.coll[R.c * n + (t - nr)];
+                const uint32_t ent =
+                    inrow ? gptr(I.rowl)[r * n + t] : gptr(I.coll)[c * n + (t - nr)];
                 const int u = (int)(ent & 0xFFFFu), other = (int)(ent >> 16);
                 if (u != v) {
                     const int su = ws.S[u];
@@ -313,15 +380,16 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         // tenure T = L + alpha (|V_0| + |C|) after the move; moving v back to
         // `old` is tabu for T iterations
         const int64_t mp = (int64_t)sc.f + sc.nC;
-        const uint32_t T = scale32(rw.x, 10u) + (uint32_t)((a.P.alpha_num * mp) / a.P.alpha_den);
+        const uint32_t T = scale32(w0, 10u) + (uint32_t)((a.P.alpha_num * mp) / a.P.alpha_den);
         const uint32_t until = itu + 1u + T;
         if (lane == 0) {
             if (k == 0 || vC)
                 atomicOr(&ws.bm[v >> 5], 1u << (v & 31));
             else
                 atomicAnd(&ws.bm[v >> 5], ~(1u << (v & 31)));
-            tabu[R.doff + v + (old ? slot_of(R, old) + 1u : 0u)] = until;
-            if (until > ws.tmax[v]) ws.tmax[v] = until;
+            gptr(tabu)[(size_t)v * TS + position_of(I, v, old)] = until;
+            const uint32_t u16 = until < 0xFFFFu ? until : 0xFFFFu;
+            if (u16 > ws.tmax[v]) ws.tmax[v] = (uint16_t)u16;
         }
         ucnt[C_MOVES]++;
         PLSE_WAVE_SYNC();
@@ -352,7 +420,7 @@ __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Sc
         for (int v = lane; v < nv; v += 64) {
             const int s = ws.S[v];
             if (s) {
-                const uint32_t rc = I.vrc[v];
+                const uint32_t rc = gptr(I.vrc)[v];
                 const int own =
                     (int)rowH[(rc & 0xFFu) * np1 + s] + (int)colH[(rc >> 8) * np1 + s] - 2;
                 if (own > 0) {
@@ -365,7 +433,7 @@ __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Sc
         if (g == 0u) break;
         const int v = (int)(0xFFFFu - (g & 0xFFFFu));
         if (lane == 0) {
-            const uint32_t rc = I.vrc[v];
+            const uint32_t rc = gptr(I.vrc)[v];
             const int old = ws.S[v];
             rowH[(rc & 0xFFu) * np1 + old] -= 1;
             colH[(rc >> 8) * np1 + old] -= 1;
@@ -380,7 +448,7 @@ __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Sc
 
 }  // namespace
 
-template <int LPV>
+template <int CH>
 __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
     const PlitsArgs a = arg_of<PlitsArgs>(L);
@@ -389,18 +457,19 @@ __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     if (ind >= a.p) return;
     int gen = a.gen_fixed;
     if (gen == 0) {
-        if (a.ctl->stop) return;
-        gen = a.ctl->gen;
+        if (gptr(a.ctl)->stop) return;
+        gen = gptr(a.ctl)->gen;
     }
     uint8_t *base = lds + (size_t)wv * a.lds_per_wave;
     WaveState ws;
     ws.S = base;
     ws.H = base + a.off_h;
     ws.bm = reinterpret_cast<uint32_t *>(base + a.off_bm);
-    ws.tmax = reinterpret_cast<uint32_t *>(base + a.off_tm);
+    ws.tmax = reinterpret_cast<uint16_t *>(base + a.off_tm);
     ws.elist = reinterpret_cast<uint16_t *>(base + a.off_el);
+    ws.ring = reinterpret_cast<uint32_t *>(base + a.off_ring);
     const DevInstance &I = a.I;
-    uint32_t *tabu = a.tabu + (size_t)ind * (I.nd + I.nv);
+    uint32_t *tabu = a.tabu + (size_t)ind * I.nv * I.ts;
     const uint8_t *src = a.S_in + (size_t)ind * I.stride;
     uint8_t *out = a.S_out + (size_t)ind * I.stride;
 
@@ -409,12 +478,13 @@ __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     for (int q = 0; q < kCounters; ++q) ucnt[q] = 0;
     uint32_t lane_cands = 0;
     Scal sc;
+    const uint32_t slot = (uint32_t)readfirst(ind);
     // phase 1 from the offspring, phase 2 from phase 1's best (both write
     // their best into `out`)
-    run_phase<LPV>(a, 1, a.P.depth1, (uint32_t)ind, (uint32_t)gen, src, out, tabu, ws, sc, ucnt,
-                   lane_cands);
-    run_phase<LPV>(a, 2, a.P.depth2, (uint32_t)ind, (uint32_t)gen, out, out, tabu, ws, sc, ucnt,
-                   lane_cands);
+    run_phase<CH>(a, 1, a.P.depth1, slot, (uint32_t)gen, src, out, tabu, ws, sc, ucnt,
+                  lane_cands);
+    run_phase<CH>(a, 2, a.P.depth2, slot, (uint32_t)gen, out, out, tabu, ws, sc, ucnt,
+                  lane_cands);
     int32_t f_final = sc.fbest;
     if (sc.cbest > 0) {
         repair(a, out, ws, sc, ucnt);
@@ -427,9 +497,9 @@ __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
 #pragma unroll
         for (int q = 0; q < kCounters; ++q)
             if (q == lane) v = ucnt[q];
-        a.cnt_out[(size_t)ind * kCounters + lane] = v;
+        gptr(a.cnt_out)[(size_t)ind * kCounters + lane] = v;
     }
-    if (lane == 0) a.f_out[ind] = f_final;
+    if (lane == 0) gptr(a.f_out)[ind] = f_final;
 }
 
 // Zero a tabu region (a fresh workspace, before the first phase uses it).
@@ -438,17 +508,16 @@ __global__ void fill_zero_kernel(const ArgList L) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t nq = a.n / 4;
     for (size_t i = t; i < nq; i += (size_t)gridDim.x * blockDim.x)
-        reinterpret_cast<uint4 *>(a.p)[i] = make_uint4(0u, 0u, 0u, 0u);
-    for (size_t i = nq * 4 + t; i < a.n; i += (size_t)gridDim.x * blockDim.x) a.p[i] = 0u;
+        gstore4(reinterpret_cast<u32x4 *>(a.p) + i, u32x4{0u, 0u, 0u, 0u});
+    for (size_t i = nq * 4 + t; i < a.n; i += (size_t)gridDim.x * blockDim.x) gptr(a.p)[i] = 0u;
 }
 
 hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
-                        int lanes_per_vertex, int waves_per_block, hipStream_t stream) {
+                        int slots_per_lane, int waves_per_block, hipStream_t stream) {
     const int blocks = (p + waves_per_block - 1) / waves_per_block;
     const size_t lds = (size_t)lds_per_wave * waves_per_block;
     const dim3 grid(blocks, count), block(64 * waves_per_block);
-    switch (lanes_per_vertex) {
-        case 1: hipLaunchKernelGGL(plits_kernel<1>, grid, block, lds, stream, L); break;
+    switch (slots_per_lane) {
         case 2: hipLaunchKernelGGL(plits_kernel<2>, grid, block, lds, stream, L); break;
         case 4: hipLaunchKernelGGL(plits_kernel<4>, grid, block, lds, stream, L); break;
         case 8: hipLaunchKernelGGL(plits_kernel<8>, grid, block, lds, stream, L); break;
@@ -463,8 +532,7 @@ hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
 }
 
 hipError_t plits_set_lds_limit(int bytes) {
-    hipError_t e = set_dynamic_lds_limit((const void *)plits_kernel<1>, bytes);
-    if (e == hipSuccess) e = set_dynamic_lds_limit((const void *)plits_kernel<2>, bytes);
+    hipError_t e = set_dynamic_lds_limit((const void *)plits_kernel<2>, bytes);
     if (e == hipSuccess) e = set_dynamic_lds_limit((const void *)plits_kernel<4>, bytes);
     if (e == hipSuccess) e = set_dynamic_lds_limit((const void *)plits_kernel<8>, bytes);
     return e;

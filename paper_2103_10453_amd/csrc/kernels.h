@@ -41,13 +41,14 @@ struct PlitsArgs {
     uint8_t *S_out;        // [p][stride]
     int32_t *f_out;        // [p]
     uint64_t *cnt_out;     // [p][kCounters]
-    uint32_t *tabu;        // [p][nd + nv], all zero between phases
+    uint32_t *tabu;        // [p][nv][ts], all zero between phases
     const Ctl *ctl;        // generation and stop flag when gen_fixed == 0
     int32_t gen_fixed;
     int32_t p;
     uint32_t seed_lo, seed_hi;
     int32_t lds_per_wave;
-    int32_t off_h, off_bm, off_tm, off_el;
+    int32_t off_h, off_bm, off_tm, off_el, off_ring;
+    int32_t qmask;         // ring capacity - 1 (a power of two)
 };
 
 struct InitArgs {
@@ -155,7 +156,7 @@ struct AuxArgs {
 // Launch entry points: `L` lists the argument blocks (device addresses) of
 // `count` instances; grid.y = count.
 hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
-                        int lanes_per_vertex, int waves_per_block, hipStream_t stream);
+                        int slots_per_lane, int waves_per_block, hipStream_t stream);
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream);
 hipError_t plits_set_lds_limit(int bytes);
 hipError_t launch_init(const ArgList &L, int count, int p, size_t lds, hipStream_t stream);

@@ -28,11 +28,15 @@ enum Tag : uint32_t {
 struct DevInstance {
     int32_t n, nv, nd, stride;       // order, |V|, sum |D*(v)|, row stride (bytes)
     int32_t l, ub;
+    int32_t ts;                      // candidate row length: |D*(v)| + 1 <= ts, ts % 8 == 0
+    int32_t pad;
     const uint16_t *vrc;             // [nv] row | column << 8
     const void *vrec;                // [nv] 32-byte records: D*(v) as a 128-bit colour
                                      //   mask, first slot offset, row | column << 8 |
                                      //   |D*(v)| << 16
-    const uint8_t *dom;              // [nd] colours of D*(v) at [first slot offset ..)
+    const uint32_t *vinfo;           // [nv] row | column << 8 | |D*(v)| << 16
+    const uint8_t *cand;             // [nv][ts] moves of v: 0 (uncolour), then D*(v)
+                                     //   ascending, zero padding
     const uint32_t *rowl, *coll;     // [n*n] vertices of row r (column c) at r*n + t:
                                      //   vertex | (its column (row) << 16)
     const uint8_t *rowc, *colc;      // [n] vertex counts per row / column

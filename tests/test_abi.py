@@ -76,7 +76,7 @@ def test_parameters_and_defaults():
         assert P.plse_get_param(h, "nn_history") == 64
         P.plse_set_param(h, "depth", 50)
         assert (P.plse_get_param(h, "depth1"), P.plse_get_param(h, "depth2")) == (0, 50)
-        for key, val in (("nope", 1), ("lanes_per_vertex", 3), ("nn_history", 65), ("alpha_den", 0),
+        for key, val in (("nope", 1), ("slots_per_lane", 3), ("nn_history", 65), ("alpha_den", 0),
                          ("waves_per_block", 3)):
             with pytest.raises(P.PlseError) as e:
                 P.plse_set_param(h, key, val)

@@ -59,23 +59,23 @@ def test_init_parity(torch_cuda, oracle_mod, name, p):
 
 
 # --- PLITS --------------------------------------------------------------------------
-@pytest.mark.parametrize("name,p,depth,lpv,wpb", [
+@pytest.mark.parametrize("name,p,depth,spl,wpb", [
     ("planted10", 64, 1000, 0, 0),
     ("planted10", 64, 1000, 8, 4),
-    ("greedy12_60", 37, 1440, 1, 1),
-    ("greedy12_60", 37, 1440, 2, 2),
+    ("greedy12_60", 37, 1440, 2, 1),
+    ("greedy12_60", 37, 1440, 4, 2),
     ("greedy20_50", 65, 4000, 4, 4),
     ("greedy20_50", 65, 4000, 0, 0),
     ("planted33_45", 20, 10890, 0, 0),
-    ("planted33_45", 20, 10890, 1, 1),
+    ("planted33_45", 20, 10890, 2, 1),
     ("greedy70_70", 9, 6000, 0, 0),
     ("greedy70_70", 9, 6000, 8, 2),
 ])
-def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, lpv, wpb):
+def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, spl, wpb):
     """S', f' and every per-individual counter equal the oracle's."""
     g = _instances()[name]
-    _say(f"plits {name} p={p} depth={depth} lpv={lpv} wpb={wpb}")
-    s = P.Solver(g, depth=depth, lanes_per_vertex=lpv, waves_per_block=wpb)
+    _say(f"plits {name} p={p} depth={depth} spl={spl} wpb={wpb}")
+    s = P.Solver(g, depth=depth, slots_per_lane=spl, waves_per_block=wpb)
     seed, gen_no = 777 + p, 3
     S0, _ = s.stage_init(p, seed)
     S1, f1, c1 = s.stage_plits(S0, gen_no, seed)
@@ -248,9 +248,9 @@ def test_solve_repeatable_and_shape_independent(torch_cuda):
     g = gen.random_greedy(20, 0.5, 7)
     _say("solve repeat")
     outs = []
-    for lpv, wpb in ((0, 0), (1, 1), (2, 2), (8, 4)):
-        s = P.Solver(g, depth=2000, lanes_per_vertex=lpv, waves_per_block=wpb)
-        for _ in range(2 if lpv == 0 and wpb == 0 else 1):
+    for spl, wpb in ((0, 0), (2, 1), (4, 2), (8, 4)):
+        s = P.Solver(g, depth=2000, slots_per_lane=spl, waves_per_block=wpb)
+        for _ in range(2 if spl == 0 and wpb == 0 else 1):
             grid, filled = s.solve(40, 3, 99)
             outs.append((grid.tobytes(), filled, s.stats()["totals"].tobytes()))
     assert len(set(outs)) == 1
