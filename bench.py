@@ -185,6 +185,8 @@ def main():
                    "plits_bytes_per_gen": bytes_gen,
                    "moves_per_gen": [int(x) for x in cnt[:, 1]],
                    "iters_per_gen": [int(x) for x in cnt[:, 0]],
+                   "cands_per_gen": [int(x) for x in cnt[:, 3]],
+                   "elig_per_gen": [int(x) for x in cnt[:, 4]],
                    "best_f_per_gen": [int(x) for x in st["best_f_per_gen"]],
                    "filled": filled, "upper_bound": s.ub,
                    "plits_moves_per_s": moves_timed / (sum(t_plits) * 1e-3)},

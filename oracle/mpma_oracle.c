@@ -47,6 +47,14 @@ uint32_t orc_fmix32(uint32_t h) {
     return h;
 }
 
+/* Tie value of move (v, k) in an iteration with tie words wv, wk: the top
+ * 16 bits of fmix32(wv ^ v) ^ fmix32(wk ^ k).  Both words are fresh every
+ * iteration, so the colours of one vertex, and one colour over several
+ * vertices, are ordered at random each time. */
+uint32_t orc_tie16(uint32_t wv, uint32_t wk, uint32_t v, uint32_t k) {
+    return (orc_fmix32(wv ^ v) ^ orc_fmix32(wk ^ k)) >> 16;
+}
+
 /* Stream tags: which random decision a draw belongs to. */
 #define TAG_INIT_ORDER 0x01u
 #define TAG_INIT_PICK  0x02u
@@ -341,9 +349,11 @@ static void plits_phase(const inst_t *I, const int64_t *P, uint64_t seed, uint32
                  * (aspiration). */
                 int adm = (it >= W->tabu[(size_t)v * (n + 1) + k]) || (F + delta < Fbest);
                 if (!adm) continue;
-                uint32_t cid = (uint32_t)(v * (n + 1) + k);
-                uint64_t key = ((uint64_t)(uint32_t)(delta + 0x80000000LL) << 32) |
-                               orc_fmix32(w[1] ^ cid);
+                /* ties: smaller tie value t(v, k) first, then smaller move
+                 * id v(n+1)+k; the scan visits ids in increasing order, so
+                 * a strict comparison of (delta, t) keeps the smallest id. */
+                uint32_t t = orc_tie16(w[1], w[2], (uint32_t)v, (uint32_t)k);
+                uint64_t key = ((uint64_t)(uint32_t)(delta + 0x80000000LL) << 32) | t;
                 if (key < best_key) { best_key = key; bv = v; bk = k; bdelta = delta; }
             }
         }

@@ -76,6 +76,8 @@ void  orc_tables(const void *h, int32_t *vrow, int32_t *vcol, int32_t *dom_off, 
 
 void  orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 uint32_t orc_fmix32(uint32_t x);
+/* Tie value of move (v, k) under tie words wv, wk (best-move ties, Section 3.3). */
+uint32_t orc_tie16(uint32_t wv, uint32_t wk, uint32_t v, uint32_t k);
 
 /* Randomised greedy legal initial colourings of slots 0..p-1. */
 void orc_init(const void *h, uint64_t seed, int32_t p, uint8_t *S, int32_t *f);

@@ -54,6 +54,8 @@ def lib():
         L.orc_philox.argtypes = [P, P, P]
         L.orc_fmix32.restype = u32
         L.orc_fmix32.argtypes = [u32]
+        L.orc_tie16.restype = u32
+        L.orc_tie16.argtypes = [u32, u32, u32, u32]
         L.orc_init.argtypes = [P, u64, i32, P, P]
         L.orc_init_slots.argtypes = [P, u64, i32, P, P, P]
         L.orc_plits.argtypes = [P, P, u64, i32, i32, P, P, P, P, P]
@@ -104,6 +106,10 @@ def philox(ctr, key) -> np.ndarray:
 
 def fmix32(x: int) -> int:
     return int(lib().orc_fmix32(x & 0xFFFFFFFF))
+
+
+def tie16(wv: int, wk: int, v: int, k: int) -> int:
+    return int(lib().orc_tie16(wv & 0xFFFFFFFF, wk & 0xFFFFFFFF, v, k))
 
 
 class Instance:

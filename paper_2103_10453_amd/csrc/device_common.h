@@ -46,7 +46,7 @@ __device__ __forceinline__ uint32_t word_of(const U4 &u, int i) {
 
 // MurmurHash3 32-bit finaliser (Appleby): a bijection, used to break ties
 // between moves of equal value without collisions.
-__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
     h ^= h >> 16;
     h *= 0x85EBCA6Bu;
     h ^= h >> 13;
@@ -55,26 +55,23 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     return h;
 }
 
-// Inverse of an odd 32-bit multiplier modulo 2^32 (Newton iteration, each
-// step doubling the number of correct low bits from the 3 that a * a = 1
-// (mod 8) gives).
-constexpr uint32_t inverse_odd(uint32_t a) {
-    uint32_t x = a;
-    for (int i = 0; i < 5; ++i) x *= 2u - a * x;
-    return x;
+// floor(x / d) for x < 2^31 and d >= 1, given m = floor((2^32 - 1) / d):
+// the high word of x * m is floor(x / d) or one less.
+__host__ __device__ inline uint32_t udiv_by(uint32_t x, uint32_t d, uint32_t m) {
+    uint32_t q = (uint32_t)(((uint64_t)x * m) >> 32);
+    if (x - q * d >= d) ++q;
+    return q;
 }
 
-// fmix32^-1: undoes the finaliser step by step (x ^= x >> 13 is undone by
-// x ^= x >> 13 ^ x >> 26; x ^= x >> 16 is its own inverse).
-__device__ __forceinline__ uint32_t fmix32_inv(uint32_t h) {
-    constexpr uint32_t i2 = inverse_odd(0xC2B2AE35u), i1 = inverse_odd(0x85EBCA6Bu);
-    static_assert(i2 * 0xC2B2AE35u == 1u && i1 * 0x85EBCA6Bu == 1u, "modular inverse");
-    h ^= h >> 16;
-    h *= i2;
-    h ^= (h >> 13) ^ (h >> 26);
-    h *= i1;
-    h ^= h >> 16;
-    return h;
+// Aspiration bound on the squeezed move scale e = 4 dc + df (|df| <= 1,
+// |V| >= 3), which orders moves as delta = |V| dc + df does.  With
+// F* - F = dfg + |V| dcg (|dfg| <= |V|) written as |V| q + r, 0 <= r < |V|,
+// delta < F* - F holds for every move with dc < q, for dc = q exactly when
+// df < r, and never for dc > q; that is e < 4 q + min(r, 2).
+__host__ __device__ inline int32_t squeezed_bound(int32_t dfg, int32_t dcg, int32_t nv) {
+    const int32_t q = dcg + (dfg < 0 ? -1 : (dfg < nv ? 0 : 1));
+    const int32_t r = dfg < 0 ? dfg + nv : (dfg < nv ? dfg : 0);
+    return 4 * q + (r < 2 ? r : 2);
 }
 
 // floor(w * m / 2^32): uniform integer in [0, m).
@@ -232,6 +229,17 @@ __device__ __forceinline__ uint64_t wave_min_u64_dpp(uint64_t v) {
     dpp_min_step<DPP_ROW_BCAST15, 0xA>(hi, lo);
     dpp_min_step<DPP_ROW_BCAST31, 0xC>(hi, lo);
     return ((uint64_t)readlane_u32(hi, 63) << 32) | readlane_u32(lo, 63);
+}
+
+// Wave minimum (u32), returned uniformly.
+__device__ __forceinline__ uint32_t wave_min_u32_dpp(uint32_t x) {
+    x = min(x, dpp_u32<DPP_QUAD_1032>(x, x));
+    x = min(x, dpp_u32<DPP_QUAD_2301>(x, x));
+    x = min(x, dpp_u32<DPP_ROW_HALF_MIRROR>(x, x));
+    x = min(x, dpp_u32<DPP_ROW_MIRROR>(x, x));
+    x = min(x, dpp_u32<DPP_ROW_BCAST15, 0xA>(x, x));
+    x = min(x, dpp_u32<DPP_ROW_BCAST31, 0xC>(x, x));
+    return readlane_u32(x, 63);
 }
 
 // Wave sum (u32), returned uniformly.

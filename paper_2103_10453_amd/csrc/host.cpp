@@ -174,9 +174,10 @@ int choose_spl(const plse_instance *h) {
 
 // PLITS per-wave LDS: S, row/column colour counts, eligibility bitmap,
 // per-vertex tabu expiry (u16), eligible-vertex list, ring of chunk
-// descriptors (one group of 64 vertices dealt while under 64 are pending).
+// descriptors (one group of 64 vertices dealt while under 64 are pending),
+// colour halves of the tie values (u16 per colour).
 struct PlitsLds {
-    int per_wave, off_h, off_bm, off_tm, off_el, off_ring, qmask;
+    int per_wave, off_h, off_bm, off_tm, off_el, off_ring, off_hk, qmask;
 };
 
 PlitsLds plits_lds(const plse_instance *h) {
@@ -189,7 +190,8 @@ PlitsLds plits_lds(const plse_instance *h) {
     L.off_tm = L.off_bm + (int)round_up((size_t)W * 4, 16);
     L.off_el = L.off_tm + (int)round_up((size_t)h->nv * 2, 16);
     L.off_ring = L.off_el + (int)round_up((size_t)h->nv * 2, 16);
-    L.per_wave = L.off_ring + qcap * 4;
+    L.off_hk = L.off_ring + qcap * 4;
+    L.per_wave = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
     L.qmask = qcap - 1;
     return L;
 }
@@ -346,6 +348,7 @@ PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
     a.off_tm = pl.off_tm;
     a.off_el = pl.off_el;
     a.off_ring = pl.off_ring;
+    a.off_hk = pl.off_hk;
     a.qmask = pl.qmask;
     return a;
 }

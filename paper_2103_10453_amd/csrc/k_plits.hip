@@ -21,8 +21,8 @@
 // Per wave (LDS): S[stride] colours, rowcnt|colcnt, the eligibility bitmap of
 //   V_0 u C(S), tmax[|V|] (latest tabu expiry written per vertex, saturating
 //   at 0xFFFF: a vertex whose tmax is not above the iteration has no tabu
-//   move), the list of eligible vertices of the iteration and a ring of
-//   chunk descriptors.
+//   move), the list of eligible vertices of the iteration, a ring of chunk
+//   descriptors and the colour halves of the iteration's tie values.
 // Per individual (HBM): tabu[|V|][TS] "allowed from" iteration of every move,
 //   read only for vertices with a live entry; all zero between phases (each
 //   phase clears the rows it wrote).
@@ -31,9 +31,11 @@
 //   1. eligible vertices V_0 u C(S) from the bitmap (wave prefix sum);
 //   2. chunks of their candidate rows, CH moves per lane and round: move value
 //      from the row/column counts, admissibility from tabu and aspiration,
-//      best (value, tie-hash) key per lane;
-//   3. DPP wave minimum picks the unique best admissible move; the tie hash
-//      is a bijection of the move id, so the key alone names the move;
+//      best key per lane: (value, tie value) above the move id v (n+1) + k,
+//      the tie value being the top half of fmix32(w1 ^ v) ^ fmix32(w2 ^ k)
+//      for the iteration's random words w1, w2;
+//   3. two DPP wave minima (key halves) pick the unique best admissible move,
+//      whose id names it;
 //   4. counts, colour, eligibility bits of the row/column vertices holding the
 //      old or new colour, tenure, tabu entry, best-solution snapshot.
 #include "device_common.h"
@@ -50,6 +52,7 @@ struct WaveState {
     uint16_t *tmax;
     uint16_t *elist;
     uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16
+    uint16_t *hk;      // [n+1] colour halves of the iteration's tie values
 };
 
 struct Scal {
@@ -195,6 +198,16 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     const int32_t phi_den = (phase == 1) ? 2 : 1;
     const uint32_t tag = (phase == 1) ? TAG_PLITS1 : TAG_PLITS2;
     const uint32_t qmask = (uint32_t)a.qmask;
+    // Move values on a 16-bit scale e ordered like delta: e = delta when the
+    // phase's values fit (phase 1, and phase 2 with |V| <= 64); otherwise
+    // e = 4 dc + df, which orders moves as |V| dc + df does since |df| <= 1
+    // and |V| >= 3.  Keys carry e + 2^15.
+    const bool squeeze = (phase == 2 && nv > 64);
+    const int32_t eA = (phase == 1) ? 1 : (squeeze ? 4 : nv);  // per unit of dc
+    const int32_t eB = (phase == 1) ? 2 : 1;                    // per unit of df
+    const uint32_t m_np1 = 0xFFFFFFFFu / (uint32_t)np1;
+    const uint32_t alpha_n = (uint32_t)a.P.alpha_num, alpha_d = (uint32_t)a.P.alpha_den;
+    const uint32_t m_alpha = 0xFFFFFFFFu / alpha_d;
     uint8_t *rowH = ws.H;
     uint8_t *colH = ws.H + n * np1;
 
@@ -205,7 +218,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     sc.fbest = sc.f;
     sc.cbest = sc.c;
     const int W = (nv + 31) >> 5;
-    uint32_t wx = 0u, wy = 0u;  // random words of iterations (it & ~63) + lane
+    uint32_t wx = 0u, wy = 0u, wz = 0u;  // random words of iterations (it & ~63) + lane
     PLSE_WAVE_SYNC();
 
     for (int64_t it = 0; it < iters; ++it) {
@@ -214,6 +227,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             const U4 rw = draw(a.seed_lo, a.seed_hi, slot, gen, tag, itu + (uint32_t)lane);
             wx = rw.x;
             wy = rw.y;
+            wz = rw.z;
         }
         // 1. eligible vertices, ascending
         uint32_t m = 0;
@@ -235,11 +249,20 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         ucnt[C_ELIG] += m;
         const uint32_t w0 = readlane_u32(wx, (int)(itu & 63u));
         const uint32_t w1 = readlane_u32(wy, (int)(itu & 63u));
+        const uint32_t w2 = readlane_u32(wz, (int)(itu & 63u));
+        for (int k = lane; k <= n; k += 64) ws.hk[k] = (uint16_t)(fmix32(w2 ^ (uint32_t)k) >> 16);
+        PLSE_WAVE_SYNC();
 
         // 2. best admissible one-move per lane over the chunk rounds.
-        //    Aspiration F + delta < F* is delta < thr (F* - F clamped to int32).
-        const int64_t gap = sc.Fbest - sc.F;
-        const int32_t thr = gap < (int64_t)INT32_MIN ? INT32_MIN : (int32_t)gap;
+        //    Aspiration F + delta < F* is e + 2^15 < teb.
+        int32_t te;
+        if (!squeeze) {
+            const int64_t gap = sc.Fbest - sc.F;  // <= 0
+            te = gap < -(1ll << 30) ? -(1 << 30) : (int32_t)gap;
+        } else {
+            te = squeezed_bound(sc.fbest - sc.f, sc.cbest - sc.c, nv);
+        }
+        const int32_t teb = te + 0x8000;
         uint64_t lbest = ~0ull;
         uint32_t lpay = 0u;
         uint32_t head = 0u, tail = 0u, g = 0u;
@@ -283,11 +306,12 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 const uint8_t *rH = rowH + r * np1;
                 const uint8_t *cH = colH + c * np1;
                 const int32_t cur = s ? ((int32_t)rH[s] + (int32_t)cH[s] - 2) : 0;
-                // delta = phi_den df + phi_num (conf(v,k) - cur), df = -1 when v
-                // was uncoloured, +1 for the uncolour move (k = 0, position 0)
-                const int32_t base = (s ? 0 : -phi_den) - phi_num * cur;
+                // e = eB df + eA (conf(v,k) - cur), df = -1 when v was
+                // uncoloured, +1 for the uncolour move (k = 0, position 0)
+                const int32_t base = 0x8000 + (s ? 0 : -eB) - eA * cur;
                 const uint32_t cid0 = (uint32_t)v * (uint32_t)np1;
-                const uint32_t vpay = (uint32_t)v | ((uint32_t)r << 14) | ((uint32_t)c << 21);
+                const uint32_t hv = fmix32(w1 ^ (uint32_t)v) >> 16;
+                const uint32_t vpay = (uint32_t)r | ((uint32_t)c << 8);
                 int kk[CH], cnt[CH];
 #pragma unroll
                 for (int t = 0; t < CH; ++t) kk[t] = (int)((cw >> (8 * t)) & 0xFFu);
@@ -296,11 +320,12 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
 #pragma unroll
                 for (int t = 0; t < CH; ++t) {
                     const int k = kk[t];
-                    const int32_t b = (t == 0 && p0 == 0) ? base + phi_den : base;
-                    const int32_t delta = phi_num * cnt[t] + b;
-                    const bool ok = (t <= lim) && (k != s) && (itu >= tv[t] || delta < thr);
-                    const uint64_t key = ((uint64_t)((uint32_t)delta + 0x80000000u) << 32) |
-                                         fmix32(w1 ^ (cid0 + (uint32_t)k));
+                    const int32_t b = (t == 0 && p0 == 0) ? base + eB : base;
+                    const int32_t eb = eA * cnt[t] + b;
+                    const bool ok = (t <= lim) && (k != s) && (itu >= tv[t] || eb < teb);
+                    const uint32_t tie = hv ^ (uint32_t)ws.hk[k];
+                    const uint64_t key =
+                        ((uint64_t)(((uint32_t)eb << 16) | tie) << 32) | (cid0 + (uint32_t)k);
                     const bool take = ok && key < lbest;
                     lbest = take ? key : lbest;
                     lpay = take ? vpay : lpay;
@@ -308,20 +333,21 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             }
             PLSE_WAVE_SYNC();
         }
-        // 3. unique best over the wave; the low key word inverts to the move id
-        const uint64_t gmin = wave_min_u64_dpp(lbest);
-        if (gmin == ~0ull) {
+        // 3. unique best over the wave: minimum of the upper key words, then
+        //    of the move ids among the lanes holding it
+        const uint32_t lhi = (uint32_t)(lbest >> 32);
+        const uint32_t ghi = wave_min_u32_dpp(lhi);
+        if (ghi == 0xFFFFFFFFu) {
             ucnt[C_IDLE]++;
             continue;
         }
-        const uint64_t who = ballot(lbest == gmin);
+        const uint32_t glo = wave_min_u32_dpp(lhi == ghi ? (uint32_t)lbest : 0xFFFFFFFFu);
+        const uint64_t who = ballot(lhi == ghi && (uint32_t)lbest == glo);
         const uint32_t pay = readlane_u32(lpay, (int)__ffsll((unsigned long long)who) - 1);
-        const int v = (int)(pay & 0x3FFFu);
-        const int r = (int)((pay >> 14) & 0x7Fu);
-        const int c = (int)((pay >> 21) & 0x7Fu);
-        const uint32_t cid = fmix32_inv((uint32_t)gmin) ^ w1;
-        const int k = (int)(cid - (uint32_t)v * (uint32_t)np1);
-        const int32_t delta = (int32_t)((uint32_t)(gmin >> 32) - 0x80000000u);
+        const int r = (int)(pay & 0xFFu);
+        const int c = (int)((pay >> 8) & 0xFFu);
+        const int v = (int)udiv_by(glo, (uint32_t)np1, m_np1);
+        const int k = (int)(glo - (uint32_t)v * (uint32_t)np1);
         const int old = ws.S[v];
         uint8_t *rH = rowH + r * np1;
         uint8_t *cH = colH + c * np1;
@@ -372,15 +398,16 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             dC += (int32_t)__popcll(ballot(enter)) - (int32_t)__popcll(ballot(leave));
         }
         const bool vC = (k != 0) && (cvk > 0);
+        const int32_t df = (k == 0 ? 1 : 0) - (old == 0 ? 1 : 0);
         sc.nC += dC + (vC ? 1 : 0) - (old ? 1 : 0);
-        sc.f += (k == 0 ? 1 : 0) - (old == 0 ? 1 : 0);
+        sc.f += df;
         sc.c += cvk - cvo;
-        sc.F += delta;
+        sc.F += (int64_t)phi_den * df + (int64_t)phi_num * (cvk - cvo);
         ucnt[C_NUPD] += 2u * (old != 0) + 2u * (k != 0);
         // tenure T = L + alpha (|V_0| + |C|) after the move; moving v back to
         // `old` is tabu for T iterations
-        const int64_t mp = (int64_t)sc.f + sc.nC;
-        const uint32_t T = scale32(w0, 10u) + (uint32_t)((a.P.alpha_num * mp) / a.P.alpha_den);
+        const uint32_t mp = (uint32_t)(sc.f + sc.nC);
+        const uint32_t T = scale32(w0, 10u) + udiv_by(alpha_n * mp, alpha_d, m_alpha);
         const uint32_t until = itu + 1u + T;
         if (lane == 0) {
             if (k == 0 || vC)
@@ -468,6 +495,7 @@ __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     ws.tmax = reinterpret_cast<uint16_t *>(base + a.off_tm);
     ws.elist = reinterpret_cast<uint16_t *>(base + a.off_el);
     ws.ring = reinterpret_cast<uint32_t *>(base + a.off_ring);
+    ws.hk = reinterpret_cast<uint16_t *>(base + a.off_hk);
     const DevInstance &I = a.I;
     uint32_t *tabu = a.tabu + (size_t)ind * I.nv * I.ts;
     const uint8_t *src = a.S_in + (size_t)ind * I.stride;

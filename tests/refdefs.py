@@ -37,6 +37,11 @@ def fmix32(h):
     return h
 
 
+def tie16(wv, wk, v, k):
+    """Tie value of move (v, k): top 16 bits of fmix32(wv ^ v) xor fmix32(wk ^ k)."""
+    return (fmix32(wv ^ v) ^ fmix32(wk ^ k)) >> 16
+
+
 def draw(seed, slot, gen, tag, idx):
     return philox4x32_10([0, slot, ((gen << 8) | tag) & M32, idx], [seed & M32, seed >> 32])
 
@@ -143,7 +148,7 @@ def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
                     delta = F(S2) - Fc
                     if not (it >= tabu.get((v, k), 0) or Fc + delta < Fbest):
                         continue
-                    key = (delta, fmix32(w[1] ^ (v * (n + 1) + k)))
+                    key = (delta, tie16(w[1], w[2], v, k), v * (n + 1) + k)
                     if best is None or key < best[0]:
                         best = (key, v, k, delta)
             if best is None:

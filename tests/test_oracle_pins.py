@@ -63,6 +63,29 @@ def test_fmix32_published_values_and_bijection(oracle_mod):
         assert y == x
 
 
+def test_tie_values_are_fair(oracle_mod):
+    """Best-move ties (Section 3.3, a best move is taken; ties at random): the
+    tie value of a move is 16 bits; over random tie words every one of
+    three tied moves comes first about a third of the time, whether they
+    are colours of one vertex, one colour on three vertices, or mixed, and
+    two moves share a value only rarely (then the smaller move id wins)."""
+    rng = np.random.default_rng(5)
+    words = [(int(a), int(b)) for a, b in rng.integers(0, 1 << 32, size=(6000, 2), dtype=np.uint64)]
+    for wv, wk in words[:50]:
+        for v, k in ((0, 0), (1249, 50), (16128, 127)):
+            assert 0 <= oracle_mod.tie16(wv, wk, v, k) < 1 << 16
+    for moves in (((7, 1), (7, 2), (7, 3)),          # colours of one vertex
+                  ((3, 5), (4, 5), (900, 5)),        # one colour, three vertices
+                  ((3, 5), (3, 6), (4, 5))):         # mixed
+        wins = [0, 0, 0]
+        for wv, wk in words:
+            t = [oracle_mod.tie16(wv, wk, v, k) for v, k in moves]
+            wins[int(np.argmin(t))] += 1
+        assert all(abs(x / len(words) - 1 / 3) < 0.03 for x in wins), (moves, wins)
+    eq = sum(oracle_mod.tie16(wv, wk, 3, 5) == oracle_mod.tie16(wv, wk, 3, 6) for wv, wk in words)
+    assert eq <= 3
+
+
 def test_philox_uniformity_chi2(oracle_mod):
     """Sanity: the top 4 bits of 16384 draws are close to uniform (chi^2, 15 dof)."""
     counts = np.zeros(16)
