@@ -7,9 +7,13 @@ HBM before the timed region; W warmup generations run first, then exactly K
 generations are timed (device synchronised on both sides).
 
 value = tabu moves executed in the K timed generations / their wall time.
-roofline: the tabu-search kernel's algorithmic state bytes per launch (from
-the per-generation counters, see plits_state_bytes; the state is LDS-resident)
-over its mean launch time from HIP events recorded on the launch stream.
+roofline: the tabu-search kernel is bound by integer ALU issue (its state is
+LDS-resident and small; see plits_alg_ops): algorithmic integer operations
+per launch, from the per-generation counters, over its mean launch time from
+HIP events recorded on the launch stream, against the int32 VALU peak.
+traffic: HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
+WRITE_SIZE summary of this command, scaled by the copy-kernel factors stated
+in it; null when the kernel sources changed since it was taken.
 cpu_baseline: the CPU oracle's PLITS on a bounded sample of the same
 generation-1 population, on the host's cores.
 """
@@ -26,9 +30,67 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import hashlib
+
 HBM_PEAK_GBS = 8000.0
-# LDS: 256 CUs x 128 B/clk x 2.4 GHz (nominal; the level that holds the state)
+# LDS: 256 CUs x 128 B/clk x 2.4 GHz (nominal)
 LDS_PEAK_GBS = 256 * 128 * 2.4
+# int32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PLITS_SOURCES = ["k_plits.hip", "device_common.h", "kernels.h", "plse_internal.h"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plits_n50_hbm.txt")
+
+
+def plits_alg_ops(cnt, n, nv):
+    """Algorithmic integer operations of one tabu-search launch.
+
+    Per candidate move (counter cands): 10 -- the move's conflict count from
+    the row and column counts (1), its value (1), tabu and aspiration tests
+    (3), tie value (1), key (2), keep-the-best comparison and select (2).
+    Per eligible vertex (elig): 10 -- its current conflicts (2), its tie hash
+    (7), bookkeeping (1).  Per iteration (iters): the eligibility bitmap scan
+    (2 per 32 vertices), the colour tie hashes (7 per colour), tenure and
+    bookkeeping (10).  Per move (moves): 8 for the counts, colour and
+    objective, 3 per row/column vertex re-checked (2|V|/n on average).  Per
+    snapshot (snaps): |V|/4 word copies.
+    cnt: counters [iters, moves, idle, cands, elig, nupd, snaps, repairs].
+    """
+    iters, moves, cands, elig, snaps = (int(cnt[0]), int(cnt[1]), int(cnt[3]), int(cnt[4]),
+                                        int(cnt[6]))
+    per_iter = 2 * ((nv + 31) // 32) + 7 * (n + 1) + 10
+    per_move = 8 + 3 * (2 * nv // n)
+    return cands * 10 + elig * 10 + iters * per_iter + moves * per_move + snaps * (nv // 4)
+
+
+def plits_sources_sha256():
+    h = hashlib.sha256()
+    for name in PLITS_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_10453_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def plits_traffic(warmup, steps, workload):
+    """HBM bytes per timed launch from the committed counter summary, or None."""
+    if workload != "n50" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    meta, rows = {}, []
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            t = line.split()
+            if len(t) >= 3 and t[0] == "#" and t[1].endswith(":"):
+                meta[t[1][:-1]] = t[2]
+            elif len(t) == 4 and t[0].isdigit():
+                rows.append((int(t[0]), float(t[2]), float(t[3])))
+    if meta.get("kernel_sources_sha256") != plits_sources_sha256():
+        return None
+    if int(meta.get("warmup", -1)) != warmup or int(meta.get("steps", -1)) != steps:
+        return None
+    ff, wf = float(meta["fetch_factor"]), float(meta["write_factor"])
+    timed = [r for r in rows if warmup < r[0] <= warmup + steps]
+    if len(timed) != steps:
+        return None
+    return sum((fk * ff + wk * wf) * 1024.0 for _, fk, wk in timed) / steps
 
 
 def plits_state_bytes(cnt, p, n, nv):
@@ -157,8 +219,12 @@ def main():
     wall = t1 - t0
     value = moves_timed / wall
     bytes_gen = [plits_state_bytes(cnt[g], p, s.n, s.nv) for g in range(timed.start, timed.stop)]
+    ops_gen = [plits_alg_ops(cnt[g], s.n, s.nv) for g in range(timed.start, timed.stop)]
     t_plits = [float(ms_plits[g]) for g in range(timed.start, timed.stop)]
-    achieved = (sum(bytes_gen) / max(len(bytes_gen), 1)) / (np.mean(t_plits) * 1e-3) / 1e9
+    t_mean = np.mean(t_plits) * 1e-3
+    achieved = (sum(ops_gen) / max(len(ops_gen), 1)) / t_mean / 1e12
+    lds_gbs = (sum(bytes_gen) / max(len(bytes_gen), 1)) / t_mean / 1e9
+    traffic = plits_traffic(args.warmup, args.steps, args.workload)
     out = {
         "metric": "tabu moves/s (n=50, pop 16384)" if args.workload == "n50"
         else f"tabu moves/s ({args.workload}, pop {p})",
@@ -178,11 +244,16 @@ def main():
                    "slots_per_lane": int(s.get_param("slots_per_lane")),
                    "vertices": s.nv, "sum_domain": s.nd,
                    "waves_per_block": int(s.get_param("waves_per_block"))},
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                     "kernel": "plits_kernel<%d>" % int(s.get_param("slots_per_lane")),
+                     "hbm_gbs": (traffic / t_mean / 1e9) if traffic else None,
+                     "hbm_frac": (traffic / t_mean / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "lds_state_gbs": lds_gbs, "lds_state_frac": lds_gbs / LDS_PEAK_GBS},
         "detail": {"moves_timed": moves_timed, "plits_ms_per_gen": t_plits,
                    "rest_ms_per_gen": [float(ms_rest[g]) for g in range(timed.start, timed.stop)],
-                   "plits_bytes_per_gen": bytes_gen,
+                   "plits_state_bytes_per_gen": bytes_gen,
+                   "plits_alg_ops_per_gen": ops_gen,
                    "moves_per_gen": [int(x) for x in cnt[:, 1]],
                    "iters_per_gen": [int(x) for x in cnt[:, 0]],
                    "cands_per_gen": [int(x) for x in cnt[:, 3]],
