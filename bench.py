@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--generations", type=int, default=0,
                     help="served: generations per request (default 50)")
     ap.add_argument("--slots-per-lane", type=int, default=0)
+    ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--population", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
@@ -198,7 +199,8 @@ def main():
         w["population"] = args.population
     p = w["population"]
     torch.cuda.set_device(0)
-    s = plse.Solver(w["grid"], depth=w["depth"], slots_per_lane=args.slots_per_lane)
+    s = plse.Solver(w["grid"], depth=w["depth"], slots_per_lane=args.slots_per_lane,
+                    waves_per_block=args.waves_per_block)
     s.ensure_workspace(p)
     stream = torch.cuda.current_stream()
 

@@ -99,6 +99,9 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *                 LDS footprint)
  * Errors: PLSE_E_PARAM.
  */
+/* Test hook (selection): "select_global_sort" 1 sorts the selection keys with
+ * the global-memory network even when they would fit in LDS (populations of
+ * at least 4096; the network always serves populations whose keys exceed LDS). */
 /* Test hook (serving): "fail_at_generation" g > 0 makes a served request end
  * with PLSE_E_FAULT after its generation g, without touching other requests. */
 int plse_set_param(plse_handle h, const char *key, int64_t value);

@@ -233,12 +233,14 @@ __device__ __forceinline__ uint64_t wave_min_u64_dpp(uint64_t v) {
 
 // Wave minimum (u32), returned uniformly.
 __device__ __forceinline__ uint32_t wave_min_u32_dpp(uint32_t x) {
-    x = min(x, dpp_u32<DPP_QUAD_1032>(x, x));
-    x = min(x, dpp_u32<DPP_QUAD_2301>(x, x));
-    x = min(x, dpp_u32<DPP_ROW_HALF_MIRROR>(x, x));
-    x = min(x, dpp_u32<DPP_ROW_MIRROR>(x, x));
-    x = min(x, dpp_u32<DPP_ROW_BCAST15, 0xA>(x, x));
-    x = min(x, dpp_u32<DPP_ROW_BCAST31, 0xC>(x, x));
+    // rows a broadcast does not reach read the identity 0xFFFFFFFF, which
+    // lets the compiler fold each move into the min as a DPP operand
+    x = min(x, dpp_u32<DPP_QUAD_1032>(0xFFFFFFFFu, x));
+    x = min(x, dpp_u32<DPP_QUAD_2301>(0xFFFFFFFFu, x));
+    x = min(x, dpp_u32<DPP_ROW_HALF_MIRROR>(0xFFFFFFFFu, x));
+    x = min(x, dpp_u32<DPP_ROW_MIRROR>(0xFFFFFFFFu, x));
+    x = min(x, dpp_u32<DPP_ROW_BCAST15, 0xA>(0xFFFFFFFFu, x));
+    x = min(x, dpp_u32<DPP_ROW_BCAST31, 0xC>(0xFFFFFFFFu, x));
     return readlane_u32(x, 63);
 }
 

@@ -91,6 +91,7 @@ struct plse_instance {
     int spl = 0;  // candidate positions per lane and round in PLITS; 0: automatic
     int wpb = 0;  // waves per block in PLITS; 0: automatic
     int fail_at = 0;  // serving test hook: end the request after this generation
+    int sel_global = 0;  // test hook: sort selection keys in global memory when possible
 
     uint8_t *ws = nullptr;
     size_t ws_bytes = 0;
@@ -175,9 +176,9 @@ int choose_spl(const plse_instance *h) {
 // PLITS per-wave LDS: S, row/column colour counts, eligibility bitmap,
 // per-vertex tabu expiry (u16), eligible-vertex list, ring of chunk
 // descriptors (one group of 64 vertices dealt while under 64 are pending),
-// colour halves of the tie values (u16 per colour).
+// colour halves of the tie values (u16 per colour), domain sizes (u8).
 struct PlitsLds {
-    int per_wave, off_h, off_bm, off_tm, off_el, off_ring, off_hk, qmask;
+    int per_wave, off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_dsz, qmask;
 };
 
 PlitsLds plits_lds(const plse_instance *h) {
@@ -191,19 +192,23 @@ PlitsLds plits_lds(const plse_instance *h) {
     L.off_el = L.off_tm + (int)round_up((size_t)h->nv * 2, 16);
     L.off_ring = L.off_el + (int)round_up((size_t)h->nv * 2, 16);
     L.off_hk = L.off_ring + qcap * 4;
-    L.per_wave = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
+    L.off_dsz = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
+    L.per_wave = L.off_dsz + (int)round_up((size_t)h->nv, 16);
     L.qmask = qcap - 1;
     return L;
 }
 
-// Waves per block maximising resident waves per CU under the LDS budget.
-int auto_wpb(int per_wave) {
+// Waves per block: the most resident waves per CU for every chunk size in
+// use; among equals the fewest waves per block, since a block keeps its LDS
+// until its slowest wave ends and searches end at very different times.
+int auto_wpb(int per_wave, const std::vector<int> &spls) {
     const int lim = max_lds_per_block();
-    int best = 1, best_waves = 0;
+    int best = 1, best_waves = -1;
     for (int w : {1, 2, 4}) {
         if (w * per_wave > lim) continue;
-        const int waves = (lim / (w * per_wave)) * w;
-        if (waves >= best_waves) {
+        int waves = 1 << 30;
+        for (int spl : spls) waves = std::min(waves, plits_waves_per_cu(spl, w, per_wave));
+        if (waves > best_waves) {
             best = w;
             best_waves = waves;
         }
@@ -212,7 +217,7 @@ int auto_wpb(int per_wave) {
 }
 
 int choose_wpb(const plse_instance *h) {
-    return h->wpb ? h->wpb : auto_wpb(plits_lds(h).per_wave);
+    return h->wpb ? h->wpb : auto_wpb(plits_lds(h).per_wave, {choose_spl(h)});
 }
 
 Layout plan(const plse_instance *h, int p) {
@@ -349,6 +354,7 @@ PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
     a.off_el = pl.off_el;
     a.off_ring = pl.off_ring;
     a.off_hk = pl.off_hk;
+    a.off_dsz = pl.off_dsz;
     a.qmask = pl.qmask;
     return a;
 }
@@ -370,8 +376,10 @@ SelectArgs make_select(plse_instance *h, int p, int gen_fixed, uint64_t seed, co
     a.ld = ld;
     a.nv = h->nv;
     a.pow2 = L.pow2_sel;
-    a.keys_in_lds =
-        select_lds_bytes(2 * p, L.pow2_sel, true) <= (size_t)max_lds_per_block() ? 1 : 0;
+    // keys in LDS when they fit; the global-memory sort needs at least two
+    // 4096-key tiles
+    const bool fits = select_lds_bytes(2 * p, L.pow2_sel, true) <= (size_t)max_lds_per_block();
+    a.keys_in_lds = (fits && !(h->sel_global && L.pow2_sel >= 8192)) || L.pow2_sel < 8192 ? 1 : 0;
     a.gen_fixed = gen_fixed;
     a.spacing = h->P.spacing;
     a.seed_lo = (uint32_t)seed;
@@ -501,8 +509,11 @@ int enqueue_rest(Session &S, hipStream_t s) {
     RC_TRY(launch_over(S.hs, &ArgBlock::close,
                        [&](const ArgList &L, int c) { return launch_close(L, c, m, s); }));
     const size_t sl = select_lds(S.hs[0], p);
-    RC_TRY(launch_over(S.hs, &ArgBlock::select,
-                       [&](const ArgList &L, int c) { return launch_select(L, c, sl, s); }));
+    const int pow2 = S.hs[0]->L.pow2_sel;
+    const bool keys_lds = S.hs[0]->args.select.keys_in_lds != 0;
+    RC_TRY(launch_over(S.hs, &ArgBlock::select, [&](const ArgList &L, int c) {
+        return launch_select(L, c, sl, pow2, keys_lds, s);
+    }));
     RC_TRY(launch_over(S.hs, &ArgBlock::gather,
                        [&](const ArgList &L, int c) { return launch_gather(L, c, p, s); }));
     const int hsize = S.hs[0]->L.hsize;
@@ -585,11 +596,14 @@ void shape_session(Session &S) {
     });
     S.lds_per_wave = 0;
     bool same_wpb = true;
+    std::vector<int> spls;
     for (plse_instance *h : S.hs) {
         S.lds_per_wave = std::max(S.lds_per_wave, plits_lds(h).per_wave);
         same_wpb = same_wpb && h->wpb == S.hs[0]->wpb;
+        if (std::find(spls.begin(), spls.end(), choose_spl(h)) == spls.end())
+            spls.push_back(choose_spl(h));
     }
-    S.wpb = (same_wpb && S.hs[0]->wpb) ? S.hs[0]->wpb : auto_wpb(S.lds_per_wave);
+    S.wpb = (same_wpb && S.hs[0]->wpb) ? S.hs[0]->wpb : auto_wpb(S.lds_per_wave, spls);
     if (S.wpb * S.lds_per_wave > max_lds_per_block()) S.wpb = 1;
 }
 
@@ -878,6 +892,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "waves_per_block") {
         if (v != 0 && v != 1 && v != 2 && v != 4) return PLSE_E_PARAM;
         h->wpb = (int)v;
+    } else if (k == "select_global_sort") {
+        if (v != 0 && v != 1) return PLSE_E_PARAM;
+        h->sel_global = (int)v;
     } else if (k == "fail_at_generation") {
         if (v < 0 || v > PLSE_MAX_GENERATIONS) return PLSE_E_PARAM;
         h->fail_at = (int)v;
@@ -904,6 +921,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "slots_per_lane") *v = choose_spl(h);
     else if (k == "waves_per_block") *v = choose_wpb(h);
     else if (k == "fail_at_generation") *v = h->fail_at;
+    else if (k == "select_global_sort") *v = h->sel_global;
     else return PLSE_E_PARAM;
     return PLSE_OK;
 }
@@ -1113,7 +1131,8 @@ int plse_stage_select(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void
     h->args.select = make_select(h, p, gen, seed, nullptr, f_all, D_all, m, accepted);
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_close(single(h, &ArgBlock::close), 1, m, s));
-    HIP_TRY(launch_select(single(h, &ArgBlock::select), 1, select_lds(h, p), s));
+    HIP_TRY(launch_select(single(h, &ArgBlock::select), 1, select_lds(h, p), h->L.pow2_sel,
+                          h->args.select.keys_in_lds != 0, s));
     return PLSE_OK;
 }
 

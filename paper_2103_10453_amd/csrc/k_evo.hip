@@ -246,6 +246,88 @@ __global__ __launch_bounds__(256) void close_kernel(const ArgList L) {
 // union of the close lists of accepted candidates) lives in an LDS bitmap.
 // Lanes take 64 candidates at a time: the candidates up to the first
 // unblocked one with a non-empty close list are decided together.
+// Selection keys of P^all: f << 48 | SELECT draw << 16 | index (the order of
+// Alg. 4: e, then a random key, then the index), ~0 beyond m.
+__device__ __forceinline__ void select_keys(const SelectArgs &a, uint32_t gen, int q,
+                                            uint64_t *K) {
+    const int x0 = q * 4;
+    U4 w{0, 0, 0, 0};
+    if (x0 < a.m) w = draw(a.seed_lo, a.seed_hi, 0u, gen, TAG_SELECT, (uint32_t)q);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int x = x0 + t;
+        K[x] = (x < a.m) ? (((uint64_t)(uint32_t)a.f_all[x] << 48) |
+                            ((uint64_t)word_of(w, t) << 16) | (uint32_t)x)
+                         : ~0ull;
+    }
+}
+
+__device__ __forceinline__ bool select_gen(const SelectArgs &a, uint32_t *gen) {
+    int g = a.gen_fixed;
+    if (g == 0) {
+        if (a.ctl->stop) return false;
+        g = a.ctl->gen;
+    }
+    *gen = (uint32_t)g;
+    return true;
+}
+
+// Key sort for populations whose keys exceed LDS: a bitonic network over the
+// global key array, tile-local stages (partner distance < kSortTile) in LDS.
+constexpr int kSortTile = 4096;
+
+__global__ __launch_bounds__(256) void select_keys_kernel(const ArgList L) {
+    const SelectArgs a = arg_of<SelectArgs>(L);
+    uint32_t gen;
+    if (!select_gen(a, &gen)) return;
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q < (a.pow2 >> 2)) select_keys(a, gen, q, a.keys_g);
+}
+
+// Pair i of a bitonic step with partner distance j: lower index.
+__device__ __forceinline__ int bitonic_lo(int i, int j) { return ((i & ~(j - 1)) << 1) | (i & (j - 1)); }
+
+__global__ __launch_bounds__(1024) void sort_tile_kernel(const ArgList L, int k_lo, int k_hi) {
+    __shared__ uint64_t t[kSortTile];
+    const SelectArgs a = arg_of<SelectArgs>(L);
+    uint32_t gen;
+    if (!select_gen(a, &gen)) return;
+    const int base = (int)blockIdx.x * kSortTile;
+    for (int q = (int)threadIdx.x; q < kSortTile; q += (int)blockDim.x) t[q] = a.keys_g[base + q];
+    __syncthreads();
+    for (int k = k_lo; k <= k_hi; k <<= 1) {
+        for (int j = min(k >> 1, kSortTile >> 1); j > 0; j >>= 1) {
+            for (int i = (int)threadIdx.x; i < (kSortTile >> 1); i += (int)blockDim.x) {
+                const int lo = bitonic_lo(i, j), hi = lo + j;
+                const bool up = ((base + lo) & k) == 0;
+                const uint64_t x = t[lo], y = t[hi];
+                if ((x > y) == up) {
+                    t[lo] = y;
+                    t[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = (int)threadIdx.x; q < kSortTile; q += (int)blockDim.x) a.keys_g[base + q] = t[q];
+}
+
+__global__ __launch_bounds__(256) void sort_global_kernel(const ArgList L, int k, int j) {
+    const SelectArgs a = arg_of<SelectArgs>(L);
+    uint32_t gen;
+    if (!select_gen(a, &gen)) return;
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= (a.pow2 >> 1)) return;
+    const int lo = bitonic_lo(i, j), hi = lo + j;
+    const bool up = (lo & k) == 0;
+    uint64_t *K = a.keys_g;
+    const uint64_t x = K[lo], y = K[hi];
+    if ((x > y) == up) {
+        K[lo] = y;
+        K[hi] = x;
+    }
+}
+
 __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
     const SelectArgs a = arg_of<SelectArgs>(L);
@@ -258,23 +340,15 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     const int m = a.m, P2 = a.pow2;
     uint32_t *blocked = reinterpret_cast<uint32_t *>(lds);          // [(m+31)/32]
     const int nbw = (m + 31) / 32;
+    // keys in LDS: generated and sorted here; else already sorted in global
+    // memory by select_keys_kernel / sort_*_kernel
     uint64_t *K = a.keys_in_lds ? reinterpret_cast<uint64_t *>(lds + ((nbw * 4 + 15) & ~15))
                                 : a.keys_g;
-    for (int q = tid; q < (P2 >> 2); q += nthr) {
-        const int x0 = q * 4;
-        U4 w{0, 0, 0, 0};
-        if (x0 < m) w = draw(a.seed_lo, a.seed_hi, 0u, (uint32_t)gen, TAG_SELECT, (uint32_t)q);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int x = x0 + t;
-            K[x] = (x < m) ? (((uint64_t)(uint32_t)a.f_all[x] << 48) |
-                              ((uint64_t)word_of(w, t) << 16) | (uint32_t)x)
-                           : ~0ull;
-        }
-    }
+    if (a.keys_in_lds)
+        for (int q = tid; q < (P2 >> 2); q += nthr) select_keys(a, (uint32_t)gen, q, K);
     for (int q = tid; q < nbw; q += nthr) blocked[q] = 0u;
     __syncthreads();
-    for (int k = 2; k <= P2; k <<= 1) {
+    for (int k = 2; k <= (a.keys_in_lds ? P2 : 1); k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = tid; i < P2; i += nthr) {
                 const int ixj = i ^ j;
@@ -591,7 +665,23 @@ hipError_t launch_close(const ArgList &L, int count, int m, hipStream_t stream) 
     return hipGetLastError();
 }
 
-hipError_t launch_select(const ArgList &L, int count, size_t lds, hipStream_t stream) {
+hipError_t launch_select(const ArgList &L, int count, size_t lds, int pow2, bool keys_in_lds,
+                         hipStream_t stream) {
+    if (!keys_in_lds) {
+        if (pow2 < kSortTile) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(select_keys_kernel, dim3((pow2 / 4 + 255) / 256, count), dim3(256), 0,
+                           stream, L);
+        const int tiles = pow2 / kSortTile;
+        hipLaunchKernelGGL(sort_tile_kernel, dim3(tiles, count), dim3(1024), 0, stream, L, 2,
+                           kSortTile);
+        for (int k = 2 * kSortTile; k <= pow2; k <<= 1) {
+            for (int j = k >> 1; j >= kSortTile; j >>= 1)
+                hipLaunchKernelGGL(sort_global_kernel, dim3((pow2 / 2 + 255) / 256, count),
+                                   dim3(256), 0, stream, L, k, j);
+            hipLaunchKernelGGL(sort_tile_kernel, dim3(tiles, count), dim3(1024), 0, stream, L, k,
+                               k);
+        }
+    }
     hipLaunchKernelGGL(select_kernel, dim3(1, count), dim3(1024), lds, stream, L);
     return hipGetLastError();
 }

@@ -22,7 +22,8 @@
 //   V_0 u C(S), tmax[|V|] (latest tabu expiry written per vertex, saturating
 //   at 0xFFFF: a vertex whose tmax is not above the iteration has no tabu
 //   move), the list of eligible vertices of the iteration, a ring of chunk
-//   descriptors and the colour halves of the iteration's tie values.
+//   descriptors, the colour halves of the iteration's tie values and the
+//   domain sizes.
 // Per individual (HBM): tabu[|V|][TS] "allowed from" iteration of every move,
 //   read only for vertices with a live entry; all zero between phases (each
 //   phase clears the rows it wrote).
@@ -53,6 +54,7 @@ struct WaveState {
     uint16_t *elist;
     uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16
     uint16_t *hk;      // [n+1] colour halves of the iteration's tie values
+    uint8_t *dsz;      // [|V|] domain sizes |D*(v)|
 };
 
 struct Scal {
@@ -61,11 +63,10 @@ struct Scal {
     int32_t fbest, cbest;
 };
 
-// Position of colour k in the candidate row of v: 0 for k = 0, else 1 + the
-// number of domain colours below k (from the vertex's 128-bit domain mask).
-__device__ __forceinline__ uint32_t position_of(const DevInstance &I, int v, int k) {
+// Position of colour k in a candidate row with 128-bit domain mask a: 0 for
+// k = 0, else 1 + the number of domain colours below k.
+__device__ __forceinline__ uint32_t position_in(const u32x4 a, int k) {
     if (k == 0) return 0u;
-    const u32x4 a = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
     const uint64_t m0 = ((uint64_t)a.y << 32) | a.x;
     const uint64_t m1 = ((uint64_t)a.w << 32) | a.z;
     if (k < 64) return 1u + (uint32_t)__popcll(m0 & ((1ull << k) - 1ull));
@@ -219,6 +220,10 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     sc.cbest = sc.c;
     const int W = (nv + 31) >> 5;
     uint32_t wx = 0u, wy = 0u, wz = 0u;  // random words of iterations (it & ~63) + lane
+    // The tabu entry of a move is written at the start of the next
+    // iteration's candidate loads (lane 0 holds it; the others hold ~0): its
+    // completion then overlaps those loads instead of stalling the move.
+    uint32_t pend_off = 0xFFFFFFFFu, pend_val = 0u;
     PLSE_WAVE_SYNC();
 
     for (int64_t it = 0; it < iters; ++it) {
@@ -229,6 +234,13 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             wy = rw.y;
             wz = rw.z;
         }
+        const uint32_t w0 = readlane_u32(wx, (int)(itu & 63u));
+        const uint32_t w1 = readlane_u32(wy, (int)(itu & 63u));
+        const uint32_t w2 = readlane_u32(wz, (int)(itu & 63u));
+        // colour halves of the tie values (written first: independent of the
+        // eligibility scan, which covers their latency)
+#pragma unroll 1
+        for (int k = lane; k <= n; k += 64) ws.hk[k] = (uint16_t)(fmix32(w2 ^ (uint32_t)k) >> 16);
         // 1. eligible vertices, ascending
         uint32_t m = 0;
         for (int wb = 0; wb < W; wb += 64) {
@@ -236,6 +248,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             uint32_t bits = (w < W) ? ws.bm[w] : 0u;
             uint32_t total;
             uint32_t pos = m + wave_excl_scan_dpp((uint32_t)__popc(bits), &total);
+#pragma unroll 1
             while (bits) {
                 const int b = __ffs(bits) - 1;
                 bits &= bits - 1u;
@@ -247,11 +260,6 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         PLSE_WAVE_SYNC();
         ucnt[C_ITERS]++;
         ucnt[C_ELIG] += m;
-        const uint32_t w0 = readlane_u32(wx, (int)(itu & 63u));
-        const uint32_t w1 = readlane_u32(wy, (int)(itu & 63u));
-        const uint32_t w2 = readlane_u32(wz, (int)(itu & 63u));
-        for (int k = lane; k <= n; k += 64) ws.hk[k] = (uint16_t)(fmix32(w2 ^ (uint32_t)k) >> 16);
-        PLSE_WAVE_SYNC();
 
         // 2. best admissible one-move per lane over the chunk rounds.
         //    Aspiration F + delta < F* is e + 2^15 < teb.
@@ -265,6 +273,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         const int32_t teb = te + 0x8000;
         uint64_t lbest = ~0ull;
         uint32_t lpay = 0u;
+        if (pend_off != 0xFFFFFFFFu) gptr(tabu)[pend_off] = pend_val;
         uint32_t head = 0u, tail = 0u, g = 0u;
         for (;;) {
             // deal the rows of the next 64 eligible vertices while fewer than
@@ -274,12 +283,13 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 uint32_t v = 0u, nch = 0u;
                 if (e < m) {
                     v = ws.elist[e];
-                    const uint32_t d = gptr(I.vinfo)[v] >> 16;
+                    const uint32_t d = ws.dsz[v];
                     nch = (d + CH) / CH;  // d + 1 positions
                     lane_cands += d;
                 }
                 uint32_t total;
                 const uint32_t at = tail + wave_excl_scan_dpp(nch, &total);
+#pragma unroll 1
                 for (uint32_t t = 0; t < nch; ++t) ws.ring[(at + t) & qmask] = v | (t << 16);
                 tail += total;
                 g += 64u;
@@ -311,7 +321,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 const int32_t base = 0x8000 + (s ? 0 : -eB) - eA * cur;
                 const uint32_t cid0 = (uint32_t)v * (uint32_t)np1;
                 const uint32_t hv = fmix32(w1 ^ (uint32_t)v) >> 16;
-                const uint32_t vpay = (uint32_t)r | ((uint32_t)c << 8);
+                const uint32_t vpay = (uint32_t)r | ((uint32_t)c << 8) | ((uint32_t)s << 16);
                 int kk[CH], cnt[CH];
 #pragma unroll
                 for (int t = 0; t < CH; ++t) kk[t] = (int)((cw >> (8 * t)) & 0xFFu);
@@ -346,29 +356,36 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         const uint32_t pay = readlane_u32(lpay, (int)__ffsll((unsigned long long)who) - 1);
         const int r = (int)(pay & 0xFFu);
         const int c = (int)((pay >> 8) & 0xFFu);
+        const int old = (int)((pay >> 16) & 0xFFu);
         const int v = (int)udiv_by(glo, (uint32_t)np1, m_np1);
         const int k = (int)(glo - (uint32_t)v * (uint32_t)np1);
-        const int old = ws.S[v];
+        // memory the apply needs, fetched together up front: v's domain mask
+        // (tabu position of the colour it leaves), the row/column vertex
+        // counts and the first 64 row/column list entries
+        const u32x4 dmask = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
+        const int nr = gptr(I.rowc)[r], nc = gptr(I.colc)[c];
+        const uint32_t ent0 = lane < nr ? gptr(I.rowl)[r * n + lane]
+                                        : (lane < nr + nc ? gptr(I.coll)[c * n + (lane - nr)] : 0u);
         uint8_t *rH = rowH + r * np1;
         uint8_t *cH = colH + c * np1;
         const int32_t cvk = k ? ((int32_t)rH[k] + (int32_t)cH[k]) : 0;
         const int32_t cvo = old ? ((int32_t)rH[old] + (int32_t)cH[old] - 2) : 0;
         PLSE_WAVE_SYNC();
-        // 4. apply: counts and colour
-        if (lane == 0) {
-            if (old) {
-                rH[old] -= 1;
-                cH[old] -= 1;
-            }
-            if (k) {
-                rH[k] += 1;
-                cH[k] += 1;
-            }
-            ws.S[v] = (uint8_t)k;
+        // 4. apply: counts (lanes 0-3, byte-packed LDS atomics, no carries:
+        //    counts stay within 0..n) and colour (lane 4)
+        if (lane < 4 && (lane < 2 ? old != 0 : k != 0)) {
+            const int col = lane < 2 ? old : k;
+            const int byte = (int)(((lane & 1) ? cH : rH) - ws.H) + col;
+            uint32_t *w = reinterpret_cast<uint32_t *>(ws.H) + (byte >> 2);
+            const uint32_t one = 1u << ((byte & 3) * 8);
+            if (lane < 2)
+                atomicSub(w, one);
+            else
+                atomicAdd(w, one);
         }
+        if (lane == 4) ws.S[v] = (uint8_t)k;
         PLSE_WAVE_SYNC();
         // eligibility of the row/column vertices holding the old or new colour
-        const int nr = gptr(I.rowc)[r], nc = gptr(I.colc)[c];
         int32_t dC = 0;
         for (int t0 = 0; t0 < nr + nc; t0 += 64) {
             const int t = t0 + lane;
@@ -376,7 +393,8 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             if (t < nr + nc) {
                 const bool inrow = t < nr;
                 const uint32_t ent =
-                    inrow ? gptr(I.rowl)[r * n + t] : gptr(I.coll)[c * n + (t - nr)];
+                    t0 == 0 ? ent0
+                            : (inrow ? gptr(I.rowl)[r * n + t] : gptr(I.coll)[c * n + (t - nr)]);
                 const int u = (int)(ent & 0xFFFFu), other = (int)(ent >> 16);
                 if (u != v) {
                     const int su = ws.S[u];
@@ -414,10 +432,11 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 atomicOr(&ws.bm[v >> 5], 1u << (v & 31));
             else
                 atomicAnd(&ws.bm[v >> 5], ~(1u << (v & 31)));
-            gptr(tabu)[(size_t)v * TS + position_of(I, v, old)] = until;
             const uint32_t u16 = until < 0xFFFFu ? until : 0xFFFFu;
             if (u16 > ws.tmax[v]) ws.tmax[v] = (uint16_t)u16;
         }
+        pend_off = lane == 0 ? (uint32_t)v * (uint32_t)TS + position_in(dmask, old) : 0xFFFFFFFFu;
+        pend_val = lane == 0 ? until : 0u;
         ucnt[C_MOVES]++;
         PLSE_WAVE_SYNC();
         if (sc.F < sc.Fbest) {
@@ -428,6 +447,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             ucnt[C_SNAPS]++;
         }
     }
+    if (pend_off != 0xFFFFFFFFu) gptr(tabu)[pend_off] = pend_val;
     PLSE_WAVE_SYNC();
     clear_tabu(I, tabu, ws);
     PLSE_WAVE_SYNC();
@@ -496,6 +516,8 @@ __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     ws.elist = reinterpret_cast<uint16_t *>(base + a.off_el);
     ws.ring = reinterpret_cast<uint32_t *>(base + a.off_ring);
     ws.hk = reinterpret_cast<uint16_t *>(base + a.off_hk);
+    ws.dsz = base + a.off_dsz;
+    for (int v = lane_id(); v < a.I.nv; v += 64) ws.dsz[v] = (uint8_t)(gptr(a.I.vinfo)[v] >> 16);
     const DevInstance &I = a.I;
     uint32_t *tabu = a.tabu + (size_t)ind * I.nv * I.ts;
     const uint8_t *src = a.S_in + (size_t)ind * I.stride;
@@ -557,6 +579,22 @@ hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
     hipLaunchKernelGGL(fill_zero_kernel, dim3(1024, count), dim3(256), 0, stream, L);
     return hipGetLastError();
+}
+
+// Resident waves per CU of a PLITS launch shape (the runtime's occupancy
+// calculation: registers, LDS and workgroup limits).
+int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave) {
+    const void *fn = slots_per_lane == 2   ? (const void *)plits_kernel<2>
+                     : slots_per_lane == 4 ? (const void *)plits_kernel<4>
+                                           : (const void *)plits_kernel<8>;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64 * waves_per_block,
+                                                     (size_t)lds_per_wave * waves_per_block) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return blocks * waves_per_block;
 }
 
 hipError_t plits_set_lds_limit(int bytes) {

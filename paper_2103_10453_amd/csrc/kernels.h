@@ -47,7 +47,7 @@ struct PlitsArgs {
     int32_t p;
     uint32_t seed_lo, seed_hi;
     int32_t lds_per_wave;
-    int32_t off_h, off_bm, off_tm, off_el, off_ring, off_hk;
+    int32_t off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_dsz;
     int32_t qmask;         // ring capacity - 1 (a power of two)
 };
 
@@ -159,6 +159,7 @@ hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
                         int slots_per_lane, int waves_per_block, hipStream_t stream);
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream);
 hipError_t plits_set_lds_limit(int bytes);
+int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave);
 hipError_t launch_init(const ArgList &L, int count, int p, size_t lds, hipStream_t stream);
 size_t init_lds_bytes(const DevInstance &I, int pow2);
 hipError_t init_set_lds_limit(int bytes);
@@ -166,7 +167,8 @@ hipError_t launch_best(const ArgList &L, int count, hipStream_t stream);
 hipError_t launch_pack(const ArgList &L, int count, size_t max_threads, hipStream_t stream);
 hipError_t launch_dist(const ArgList &L, int count, int m, int B, hipStream_t stream);
 hipError_t launch_close(const ArgList &L, int count, int m, hipStream_t stream);
-hipError_t launch_select(const ArgList &L, int count, size_t lds, hipStream_t stream);
+hipError_t launch_select(const ArgList &L, int count, size_t lds, int pow2, bool keys_in_lds,
+                         hipStream_t stream);
 size_t select_lds_bytes(int m, int pow2, bool keys_in_lds);
 hipError_t launch_gather(const ArgList &L, int count, int p, hipStream_t stream);
 hipError_t launch_hash(const ArgList &L, int count, int p, int hsize, hipStream_t stream);

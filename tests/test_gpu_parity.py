@@ -140,12 +140,16 @@ def test_distances_parity(torch_cuda, oracle_mod, name, m):
     np.testing.assert_array_equal(_np(D).astype(np.int32), Do)
 
 
-@pytest.mark.parametrize("p,gen_no,seed", [(2, 1, 1), (64, 3, 5), (100, 7, 11), (300, 2, 13),
-                                           (1024, 4, 17)])
-def test_select_parity(torch_cuda, oracle_mod, p, gen_no, seed):
+@pytest.mark.parametrize("p,gen_no,seed,global_sort", [(2, 1, 1, 0), (64, 3, 5, 0),
+                                                       (100, 7, 11, 0), (300, 2, 13, 0),
+                                                       (1024, 4, 17, 0), (2100, 5, 19, 1),
+                                                       (4097, 6, 23, 1)])
+def test_select_parity(torch_cuda, oracle_mod, p, gen_no, seed, global_sort):
+    """Alg. 4 on the GPU equals the oracle; global_sort exercises the key
+    sort used when the keys exceed LDS (tiles plus global merge steps)."""
     g = gen.random_greedy(20, 0.5, 7)
-    _say(f"select p={p}")
-    s = P.Solver(g)
+    _say(f"select p={p} global_sort={global_sort}")
+    s = P.Solver(g, select_global_sort=global_sort)
     I = oracle_mod.Instance(g)
     rng = np.random.default_rng(seed)
     m = 2 * p
