@@ -44,7 +44,7 @@ int colour_bits(int n) {
 
 // Offsets of every device array of one handle, for a population p.
 struct Layout {
-    size_t vrc, vrec, cand, vinfo, rowl, coll, rowc, colc;
+    size_t vrc, vrec, cand, vinfo, nbr;
     size_t args, ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
     size_t tabu, planes, D, deg, adj, keys, rej, acc, hkeys, hvals, partner, dpart;
@@ -84,8 +84,9 @@ struct plse_instance {
     std::vector<uint32_t> vrec;  // 8 words per vertex
     std::vector<uint8_t> cand;   // [nv][ts] candidate rows: 0, D*(v) ascending, 0 padding
     std::vector<uint32_t> vinfo; // [nv] row | column << 8 | |D*(v)| << 16
-    std::vector<uint32_t> rowl, coll;
-    std::vector<uint8_t> rowc, colc;
+    int nl = 0;                   // neighbour list length per vertex: 2(n-1)
+    std::vector<uint32_t> nbr;    // [nv][nl] row then column vertices of v (not v):
+                                  //   u | other coordinate << 16 | column flag << 31
 
     Params P{};
     int spl = 0;  // candidate positions per lane and round in PLITS; 0: automatic
@@ -164,7 +165,7 @@ int choose_spl(const plse_instance *h) {
     double best = 0.0;
     for (int ch : {2, 4, 8}) {
         double cost = 0.0;
-        for (int v = 0; v < h->nv; ++v) cost += (double)(((h->vinfo[v] >> 16) + ch) / ch) * (ch + 1.5);
+        for (int v = 0; v < h->nv; ++v) cost += (double)((((h->vinfo[v] >> 16) & 0xFFu) + ch) / ch) * (ch + 1.5);
         if (ch == 2 || cost < best) {
             best = cost;
             pick = ch;
@@ -174,11 +175,13 @@ int choose_spl(const plse_instance *h) {
 }
 
 // PLITS per-wave LDS: S, row/column colour counts, eligibility bitmap,
-// per-vertex tabu expiry (u16), eligible-vertex list, ring of chunk
-// descriptors (one group of 64 vertices dealt while under 64 are pending),
-// colour halves of the tie values (u16 per colour), domain sizes (u8).
+// per-vertex relative tabu expiry marks (u8) and the bitmap of vertices with
+// tabu entries, 64 staged eligible vertices, ring of chunk descriptors (one
+// group of 64 vertices dealt while under 64 are pending), colour halves of
+// the tie values (u16 per colour), bit planes of the chunk counts.
 struct PlitsLds {
-    int per_wave, off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_dsz, qmask;
+    int per_wave, off_h, off_bm, off_tm, off_dirty, off_el, off_ring, off_hk, off_planes;
+    int qmask, nplanes;
 };
 
 PlitsLds plits_lds(const plse_instance *h) {
@@ -189,11 +192,14 @@ PlitsLds plits_lds(const plse_instance *h) {
     L.off_h = h->stride;
     L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
     L.off_tm = L.off_bm + (int)round_up((size_t)W * 4, 16);
-    L.off_el = L.off_tm + (int)round_up((size_t)h->nv * 2, 16);
-    L.off_ring = L.off_el + (int)round_up((size_t)h->nv * 2, 16);
+    L.off_dirty = L.off_tm + (int)round_up((size_t)h->nv, 16);
+    L.off_el = L.off_dirty + (int)round_up((size_t)W * 4, 16);
+    L.off_ring = L.off_el + 128;
     L.off_hk = L.off_ring + qcap * 4;
-    L.off_dsz = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
-    L.per_wave = L.off_dsz + (int)round_up((size_t)h->nv, 16);
+    L.off_planes = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
+    L.nplanes = 0;
+    while ((h->dmax / ch) >> L.nplanes) ++L.nplanes;
+    L.per_wave = L.off_planes + (int)round_up((size_t)L.nplanes * W * 4, 16);
     L.qmask = qcap - 1;
     return L;
 }
@@ -235,10 +241,7 @@ Layout plan(const plse_instance *h, int p) {
     L.vrec = take(32 * nv);
     L.cand = take(nv * (size_t)h->ts);
     L.vinfo = take(4 * nv);
-    L.rowl = take(4 * n * n);
-    L.coll = take(4 * n * n);
-    L.rowc = take(n);
-    L.colc = take(n);
+    L.nbr = take(4 * nv * (size_t)std::max(h->nl, 1));
     L.args = take(sizeof(ArgBlock));
     L.ctl = take(sizeof(Ctl));
     L.stats = take(sizeof(GenStat) * PLSE_MAX_GENERATIONS);
@@ -292,10 +295,8 @@ DevInstance dev_instance(plse_instance *h) {
     I.vrec = at<void>(h, L.vrec);
     I.cand = at<uint8_t>(h, L.cand);
     I.vinfo = at<uint32_t>(h, L.vinfo);
-    I.rowl = at<uint32_t>(h, L.rowl);
-    I.coll = at<uint32_t>(h, L.coll);
-    I.rowc = at<uint8_t>(h, L.rowc);
-    I.colc = at<uint8_t>(h, L.colc);
+    I.nl = h->nl;
+    I.nbr = at<uint32_t>(h, L.nbr);
     return I;
 }
 
@@ -309,10 +310,7 @@ int upload_instance(plse_instance *h, hipStream_t s) {
     HIP_TRY(put(L.vrec, h->vrec.data(), 4 * h->vrec.size()));
     HIP_TRY(put(L.cand, h->cand.data(), h->cand.size()));
     HIP_TRY(put(L.vinfo, h->vinfo.data(), 4 * h->vinfo.size()));
-    HIP_TRY(put(L.rowl, h->rowl.data(), 4 * h->rowl.size()));
-    HIP_TRY(put(L.coll, h->coll.data(), 4 * h->coll.size()));
-    HIP_TRY(put(L.rowc, h->rowc.data(), h->rowc.size()));
-    HIP_TRY(put(L.colc, h->colc.data(), h->colc.size()));
+    HIP_TRY(put(L.nbr, h->nbr.data(), 4 * h->nbr.size()));
     return PLSE_OK;
 }
 
@@ -354,7 +352,9 @@ PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
     a.off_el = pl.off_el;
     a.off_ring = pl.off_ring;
     a.off_hk = pl.off_hk;
-    a.off_dsz = pl.off_dsz;
+    a.off_dirty = pl.off_dirty;
+    a.off_planes = pl.off_planes;
+    a.nplanes = pl.nplanes;
     a.qmask = pl.qmask;
     return a;
 }
@@ -757,10 +757,8 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
     // numbered row-major.
     uint64_t full[2] = {0, 0};
     for (int k = 1; k <= n; ++k) full[k >> 6] |= 1ull << (k & 63);
-    h->rowc.assign(n, 0);
-    h->colc.assign(n, 0);
-    h->rowl.assign((size_t)n * n, 0);
-    h->coll.assign((size_t)n * n, 0);
+    std::vector<int> rowc(n, 0), colc(n, 0);
+    std::vector<uint32_t> rowl((size_t)n * n, 0), coll((size_t)n * n, 0);
     std::vector<uint64_t> dmask;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
@@ -777,8 +775,8 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
             h->vrc.push_back((uint16_t)(i | (j << 8)));
             dmask.push_back(d0);
             dmask.push_back(d1);
-            h->rowl[(size_t)i * n + h->rowc[i]++] = (uint32_t)v | ((uint32_t)j << 16);
-            h->coll[(size_t)j * n + h->colc[j]++] = (uint32_t)v | ((uint32_t)i << 16);
+            rowl[(size_t)i * n + rowc[i]++] = (uint32_t)v | ((uint32_t)j << 16);
+            coll[(size_t)j * n + colc[j]++] = (uint32_t)v | ((uint32_t)i << 16);
         }
     h->ub = (h->l == 1) ? n * n - 2 : n * n - h->l;
     // vertex records: 128-bit domain mask, first slot (sum of earlier domain
@@ -786,6 +784,8 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
     // (the moves 0, D*(v) ascending, zero padded to ts positions)
     h->vrec.assign((size_t)h->nv * 8, 0);
     h->vinfo.assign(h->nv, 0);
+    h->nl = std::max(2 * (n - 1), 1);
+    h->nbr.assign((size_t)h->nv * h->nl, 0);
     uint32_t off = 0;
     for (int v = 0; v < h->nv; ++v) {
         uint32_t *r = &h->vrec[(size_t)v * 8];
@@ -797,7 +797,16 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
                                       __builtin_popcountll(dmask[2 * v + 1]));
         r[4] = off;
         r[5] = (uint32_t)h->vrc[v] | (d << 16);
-        h->vinfo[v] = (uint32_t)h->vrc[v] | (d << 16);
+        // neighbours: the other vertices of v's row, then of its column
+        const int i = h->vrc[v] & 0xFF, j = h->vrc[v] >> 8;
+        uint32_t deg = 0;
+        for (int t = 0; t < rowc[i]; ++t)
+            if ((int)(rowl[(size_t)i * n + t] & 0xFFFFu) != v)
+                h->nbr[(size_t)v * h->nl + deg++] = rowl[(size_t)i * n + t];
+        for (int t = 0; t < colc[j]; ++t)
+            if ((int)(coll[(size_t)j * n + t] & 0xFFFFu) != v)
+                h->nbr[(size_t)v * h->nl + deg++] = coll[(size_t)j * n + t] | 0x80000000u;
+        h->vinfo[v] = (uint32_t)h->vrc[v] | (d << 16) | (deg << 24);
         h->dmax = std::max(h->dmax, (int)d);
         off += d;
     }

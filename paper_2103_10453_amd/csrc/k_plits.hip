@@ -19,11 +19,12 @@
 // the domain sizes are.
 //
 // Per wave (LDS): S[stride] colours, rowcnt|colcnt, the eligibility bitmap of
-//   V_0 u C(S), tmax[|V|] (latest tabu expiry written per vertex, saturating
-//   at 0xFFFF: a vertex whose tmax is not above the iteration has no tabu
-//   move), the list of eligible vertices of the iteration, a ring of chunk
-//   descriptors, the colour halves of the iteration's tie values and the
-//   domain sizes.
+//   V_0 u C(S), tm8[|V|] (latest tabu expiry written per vertex, relative to
+//   a base advanced by 128 iterations at a time, 255 = "treat as live"; a
+//   vertex not live has no tabu move), a bitmap of vertices with tabu entries
+//   this phase, the 64 eligible vertices being dealt, a ring of chunk
+//   descriptors, the colour halves of the iteration's tie values and bit
+//   planes of the vertices' chunk counts.
 // Per individual (HBM): tabu[|V|][TS] "allowed from" iteration of every move,
 //   read only for vertices with a live entry; all zero between phases (each
 //   phase clears the rows it wrote).
@@ -50,11 +51,21 @@ struct WaveState {
     uint8_t *S;
     uint8_t *H;        // rowcnt [n][n+1] then colcnt [n][n+1]
     uint32_t *bm;
-    uint16_t *tmax;
-    uint16_t *elist;
+    uint8_t *tm8;      // [|V|] tabu expiry relative to the base (0: none, 255: sticky)
+    uint32_t *dirty;   // [W] vertices with tabu entries written this phase
+    uint16_t *stage;   // [64] the eligible vertices being dealt
     uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16
     uint16_t *hk;      // [n+1] colour halves of the iteration's tie values
-    uint8_t *dsz;      // [|V|] domain sizes |D*(v)|
+    uint32_t *planes;  // [B][W] bit b of floor(|D*(v)| / CH) (chunks per row - 1)
+    int nplanes;
+};
+
+// Per-individual counters of one launch (moves = iterations - idle ones).
+// Iterations per phase are at most 2^31 - 1, so the per-iteration ones fit 32
+// bits; eligible-vertex and update sums take 64.
+struct Cnt {
+    uint32_t iters, idle, snaps, repairs;
+    uint64_t elig, nupd;
 };
 
 struct Scal {
@@ -115,7 +126,8 @@ __device__ void setup_state(const DevInstance &I, const uint8_t *src, const Wave
         }
         ws.bm[w] = bits;
     }
-    for (int v = lane; v < nv; v += 64) ws.tmax[v] = 0;
+    for (int q = lane; q < (nv + 3) >> 2; q += 64) reinterpret_cast<uint32_t *>(ws.tm8)[q] = 0u;
+    for (int w = lane; w < W; w += 64) ws.dirty[w] = 0u;
     PLSE_WAVE_SYNC();
     sc.f = (int32_t)wave_sum_u32_dpp(f);
     sc.c = (int32_t)(wave_sum_u32_dpp(c2) >> 1);  // each conflicting edge seen twice
@@ -127,11 +139,11 @@ __device__ __forceinline__ void snapshot(const DevInstance &I, const uint8_t *S,
         gstore4(reinterpret_cast<u32x4 *>(dst) + q, reinterpret_cast<const u32x4 *>(S)[q]);
 }
 
-// Zero the tabu rows this phase wrote (their vertices have tmax > 0).
+// Zero the tabu rows this phase wrote.
 __device__ void clear_tabu(const DevInstance &I, uint32_t *tabu, const WaveState &ws) {
     const int q4 = I.ts >> 2;
     for (int v = lane_id(); v < I.nv; v += 64) {
-        if (ws.tmax[v]) {
+        if ((ws.dirty[v >> 5] >> (v & 31)) & 1u) {
             u32x4 *tb = reinterpret_cast<u32x4 *>(tabu + (size_t)v * I.ts);
             for (int t = 0; t < q4; ++t) gstore4(tb + t, u32x4{0u, 0u, 0u, 0u});
         }
@@ -190,7 +202,7 @@ struct Chunk<8> {
 template <int CH>
 __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t slot,
                           uint32_t gen, const uint8_t *src, uint8_t *out, uint32_t *tabu,
-                          const WaveState &ws, Scal &sc, uint64_t *ucnt, uint32_t &lane_cands) {
+                          const WaveState &ws, Scal &sc, Cnt &ucnt, uint32_t &lane_cands) {
     const DevInstance &I = a.I;
     const int lane = lane_id();
     const int n = I.n, nv = I.nv, np1 = n + 1, TS = I.ts;
@@ -206,7 +218,6 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     const bool squeeze = (phase == 2 && nv > 64);
     const int32_t eA = (phase == 1) ? 1 : (squeeze ? 4 : nv);  // per unit of dc
     const int32_t eB = (phase == 1) ? 2 : 1;                    // per unit of df
-    const uint32_t m_np1 = 0xFFFFFFFFu / (uint32_t)np1;
     const uint32_t alpha_n = (uint32_t)a.P.alpha_num, alpha_d = (uint32_t)a.P.alpha_den;
     const uint32_t m_alpha = 0xFFFFFFFFu / alpha_d;
     uint8_t *rowH = ws.H;
@@ -224,6 +235,10 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     // iteration's candidate loads (lane 0 holds it; the others hold ~0): its
     // completion then overlaps those loads instead of stalling the move.
     uint32_t pend_off = 0xFFFFFFFFu, pend_val = 0u;
+    // likewise the expiry mark of the moved vertex, raised at the start of
+    // the next iteration (under the eligibility scan)
+    uint32_t pend_tv = 0xFFFFFFFFu, pend_tu = 0u;
+    uint32_t tbase = 0u;  // base of the relative expiry marks
     PLSE_WAVE_SYNC();
 
     for (int64_t it = 0; it < iters; ++it) {
@@ -234,6 +249,27 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             wy = rw.y;
             wz = rw.z;
         }
+        if ((itu & 127u) == 0u && itu != 0u) {
+            // advance the base: marks drop by 128 (expired ones to 0), 255 stays
+            tbase += 128u;
+            PLSE_WAVE_SYNC();
+            for (int q = lane; q < (nv + 3) >> 2; q += 64) {
+                const uint32_t x = reinterpret_cast<uint32_t *>(ws.tm8)[q];
+                uint32_t y = 0u;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t b = (x >> (8 * t)) & 0xFFu;
+                    y |= (b == 255u ? 255u : (b > 128u ? b - 128u : 0u)) << (8 * t);
+                }
+                reinterpret_cast<uint32_t *>(ws.tm8)[q] = y;
+            }
+            PLSE_WAVE_SYNC();
+        }
+        if (lane == 0 && pend_tv != 0xFFFFFFFFu) {
+            const uint32_t rel = pend_tu - tbase;  // >= 1
+            const uint32_t mark = rel > 254u ? 255u : rel;
+            if (mark > ws.tm8[pend_tv]) ws.tm8[pend_tv] = (uint8_t)mark;
+        }
         const uint32_t w0 = readlane_u32(wx, (int)(itu & 63u));
         const uint32_t w1 = readlane_u32(wy, (int)(itu & 63u));
         const uint32_t w2 = readlane_u32(wz, (int)(itu & 63u));
@@ -241,7 +277,8 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         // eligibility scan, which covers their latency)
 #pragma unroll 1
         for (int k = lane; k <= n; k += 64) ws.hk[k] = (uint16_t)(fmix32(w2 ^ (uint32_t)k) >> 16);
-        // 1. eligible vertices, ascending
+        // 1. eligible vertices (ascending rank over the bitmap): their number
+        //    m, and the first 64 of them staged for dealing
         uint32_t m = 0;
         for (int wb = 0; wb < W; wb += 64) {
             const int w = wb + lane;
@@ -249,17 +286,17 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             uint32_t total;
             uint32_t pos = m + wave_excl_scan_dpp((uint32_t)__popc(bits), &total);
 #pragma unroll 1
-            while (bits) {
+            while (bits && pos < 64u) {
                 const int b = __ffs(bits) - 1;
                 bits &= bits - 1u;
-                ws.elist[pos++] = (uint16_t)(w * 32 + b);
+                ws.stage[pos++] = (uint16_t)(w * 32 + b);
             }
             m += total;
         }
         if (m == 0) break;  // F = 0: complete legal colouring
         PLSE_WAVE_SYNC();
-        ucnt[C_ITERS]++;
-        ucnt[C_ELIG] += m;
+        ucnt.iters++;
+        ucnt.elig += m;
 
         // 2. best admissible one-move per lane over the chunk rounds.
         //    Aspiration F + delta < F* is e + 2^15 < teb.
@@ -271,21 +308,48 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             te = squeezed_bound(sc.fbest - sc.f, sc.cbest - sc.c, nv);
         }
         const int32_t teb = te + 0x8000;
-        uint64_t lbest = ~0ull;
-        uint32_t lpay = 0u;
+        // per lane: upper key word of its best move (value, tie value), the
+        // move's vertex and colour, and the vertex's payload.  A lane meets
+        // its moves in ascending id order, so keeping the first of equal
+        // upper words keeps the smallest id among them.
+        uint32_t lhi = 0xFFFFFFFFu, lv = 0u, lk = 0u, lpay = 0u;
         if (pend_off != 0xFFFFFFFFu) gptr(tabu)[pend_off] = pend_val;
         uint32_t head = 0u, tail = 0u, g = 0u;
         for (;;) {
             // deal the rows of the next 64 eligible vertices while fewer than
             // a round of chunks is pending
             while (tail - head < 64u && g < m) {
+                if (g > 0) {
+                    // stage eligible vertices of rank g .. g+63 (the bitmap
+                    // does not change within the iteration)
+                    PLSE_WAVE_SYNC();
+                    uint32_t base = 0;
+                    for (int wb = 0; wb < W && base < g + 64u; wb += 64) {
+                        const int w = wb + lane;
+                        uint32_t bits = (w < W) ? ws.bm[w] : 0u;
+                        uint32_t total;
+                        uint32_t pos = base + wave_excl_scan_dpp((uint32_t)__popc(bits), &total);
+#pragma unroll 1
+                        while (bits && pos < g + 64u) {
+                            const int b = __ffs(bits) - 1;
+                            bits &= bits - 1u;
+                            if (pos >= g) ws.stage[pos - g] = (uint16_t)(w * 32 + b);
+                            ++pos;
+                        }
+                        base += total;
+                    }
+                    PLSE_WAVE_SYNC();
+                }
                 const uint32_t e = g + (uint32_t)lane;
                 uint32_t v = 0u, nch = 0u;
                 if (e < m) {
-                    v = ws.elist[e];
-                    const uint32_t d = ws.dsz[v];
-                    nch = (d + CH) / CH;  // d + 1 positions
-                    lane_cands += d;
+                    v = ws.stage[lane];
+                    uint32_t code = 0u;
+#pragma unroll
+                    for (int b = 0; b < 6; ++b)
+                        if (b < ws.nplanes)
+                            code |= ((ws.planes[b * W + (int)(v >> 5)] >> (v & 31u)) & 1u) << b;
+                    nch = code + 1u;  // ceil((d + 1) / CH)
                 }
                 uint32_t total;
                 const uint32_t at = tail + wave_excl_scan_dpp(nch, &total);
@@ -303,8 +367,8 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 const int v = (int)(ent & 0xFFFFu);
                 const int p0 = (int)(ent >> 16) * CH;
                 const int s = ws.S[v];
-                const uint32_t tm = ws.tmax[v];
-                const bool live = tm > itu || tm == 0xFFFFu;
+                const uint32_t tm = ws.tm8[v];
+                const bool live = tm == 255u || tm > itu - tbase;
                 const uint32_t vi = gptr(I.vinfo)[v];
                 const auto cw = Chunk<CH>::colours(I.cand + (size_t)v * TS + p0);
                 uint32_t tv[CH];
@@ -312,60 +376,73 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 for (int t = 0; t < CH; ++t) tv[t] = 0u;
                 if (live) Chunk<CH>::tabu(tabu + (size_t)v * TS + p0, tv);
                 const int r = (int)(vi & 0xFFu), c = (int)((vi >> 8) & 0xFFu);
-                const int lim = (int)(vi >> 16) - p0;  // positions t <= lim exist
+                const int lim = (int)((vi >> 16) & 0xFFu) - p0;  // positions t <= lim exist
+                if (p0 == 0) lane_cands += (vi >> 16) & 0xFFu;
                 const uint8_t *rH = rowH + r * np1;
                 const uint8_t *cH = colH + c * np1;
                 const int32_t cur = s ? ((int32_t)rH[s] + (int32_t)cH[s] - 2) : 0;
                 // e = eB df + eA (conf(v,k) - cur), df = -1 when v was
                 // uncoloured, +1 for the uncolour move (k = 0, position 0)
                 const int32_t base = 0x8000 + (s ? 0 : -eB) - eA * cur;
-                const uint32_t cid0 = (uint32_t)v * (uint32_t)np1;
                 const uint32_t hv = fmix32(w1 ^ (uint32_t)v) >> 16;
-                const uint32_t vpay = (uint32_t)r | ((uint32_t)c << 8) | ((uint32_t)s << 16);
+                // winner payload: row, column, current colour, degree
+                const uint32_t vpay =
+                    (uint32_t)r | ((uint32_t)c << 8) | ((uint32_t)s << 16) | (vi & 0xFF000000u);
+                // all LDS reads of the chunk issued together
                 int kk[CH], cnt[CH];
+                uint32_t hkv[CH];
 #pragma unroll
                 for (int t = 0; t < CH; ++t) kk[t] = (int)((cw >> (8 * t)) & 0xFFu);
 #pragma unroll
                 for (int t = 0; t < CH; ++t) cnt[t] = (int)rH[kk[t]] + (int)cH[kk[t]];
+#pragma unroll
+                for (int t = 0; t < CH; ++t) hkv[t] = ws.hk[kk[t]];
+                bool took = false;
 #pragma unroll
                 for (int t = 0; t < CH; ++t) {
                     const int k = kk[t];
                     const int32_t b = (t == 0 && p0 == 0) ? base + eB : base;
                     const int32_t eb = eA * cnt[t] + b;
                     const bool ok = (t <= lim) && (k != s) && (itu >= tv[t] || eb < teb);
-                    const uint32_t tie = hv ^ (uint32_t)ws.hk[k];
-                    const uint64_t key =
-                        ((uint64_t)(((uint32_t)eb << 16) | tie) << 32) | (cid0 + (uint32_t)k);
-                    const bool take = ok && key < lbest;
-                    lbest = take ? key : lbest;
-                    lpay = take ? vpay : lpay;
+                    const uint32_t hi = ((uint32_t)eb << 16) | (hv ^ hkv[t]);
+                    const bool take = ok && hi < lhi;
+                    lhi = take ? hi : lhi;
+                    lk = take ? (uint32_t)k : lk;
+                    took = took || take;
                 }
+                lv = took ? (uint32_t)v : lv;
+                lpay = took ? vpay : lpay;
             }
             PLSE_WAVE_SYNC();
         }
         // 3. unique best over the wave: minimum of the upper key words, then
         //    of the move ids among the lanes holding it
-        const uint32_t lhi = (uint32_t)(lbest >> 32);
         const uint32_t ghi = wave_min_u32_dpp(lhi);
         if (ghi == 0xFFFFFFFFu) {
-            ucnt[C_IDLE]++;
+            ucnt.idle++;
             continue;
         }
-        const uint32_t glo = wave_min_u32_dpp(lhi == ghi ? (uint32_t)lbest : 0xFFFFFFFFu);
-        const uint64_t who = ballot(lhi == ghi && (uint32_t)lbest == glo);
-        const uint32_t pay = readlane_u32(lpay, (int)__ffsll((unsigned long long)who) - 1);
+        // the move id of the lane holding the minimum (a second minimum over
+        // move ids only when several lanes share the upper word)
+        uint64_t who = ballot(lhi == ghi);
+        if (__popcll(who) != 1) {
+            const uint32_t lcid = lv * (uint32_t)np1 + lk;
+            const uint32_t glo = wave_min_u32_dpp(lhi == ghi ? lcid : 0xFFFFFFFFu);
+            who = ballot(lhi == ghi && lcid == glo);
+        }
+        const int wl = (int)__ffsll((unsigned long long)who) - 1;
+        const uint32_t pay = readlane_u32(lpay, wl);
+        const int v = (int)readlane_u32(lv, wl);
+        const int k = (int)readlane_u32(lk, wl);
         const int r = (int)(pay & 0xFFu);
         const int c = (int)((pay >> 8) & 0xFFu);
         const int old = (int)((pay >> 16) & 0xFFu);
-        const int v = (int)udiv_by(glo, (uint32_t)np1, m_np1);
-        const int k = (int)(glo - (uint32_t)v * (uint32_t)np1);
+        const int deg = (int)(pay >> 24);
         // memory the apply needs, fetched together up front: v's domain mask
-        // (tabu position of the colour it leaves), the row/column vertex
-        // counts and the first 64 row/column list entries
+        // (tabu position of the colour it leaves) and its first 64 neighbours
         const u32x4 dmask = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
-        const int nr = gptr(I.rowc)[r], nc = gptr(I.colc)[c];
-        const uint32_t ent0 = lane < nr ? gptr(I.rowl)[r * n + lane]
-                                        : (lane < nr + nc ? gptr(I.coll)[c * n + (lane - nr)] : 0u);
+        const uint32_t *nb = I.nbr + (size_t)v * I.nl;
+        const uint32_t ent0 = lane < deg ? gptr(nb)[lane] : 0u;
         uint8_t *rH = rowH + r * np1;
         uint8_t *cH = colH + c * np1;
         const int32_t cvk = k ? ((int32_t)rH[k] + (int32_t)cH[k]) : 0;
@@ -387,16 +464,14 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         PLSE_WAVE_SYNC();
         // eligibility of the row/column vertices holding the old or new colour
         int32_t dC = 0;
-        for (int t0 = 0; t0 < nr + nc; t0 += 64) {
+        for (int t0 = 0; t0 < deg; t0 += 64) {
             const int t = t0 + lane;
             bool enter = false, leave = false;
-            if (t < nr + nc) {
-                const bool inrow = t < nr;
-                const uint32_t ent =
-                    t0 == 0 ? ent0
-                            : (inrow ? gptr(I.rowl)[r * n + t] : gptr(I.coll)[c * n + (t - nr)]);
-                const int u = (int)(ent & 0xFFFFu), other = (int)(ent >> 16);
-                if (u != v) {
+            if (t < deg) {
+                const uint32_t ent = t0 == 0 ? ent0 : gptr(nb)[t];
+                const bool inrow = (ent >> 31) == 0;
+                const int u = (int)(ent & 0xFFFFu), other = (int)((ent >> 16) & 0x7FFFu);
+                {
                     const int su = ws.S[u];
                     if (su != 0 && (su == old || su == k)) {
                         const int cu = inrow ? (int)rH[su] + (int)colH[other * np1 + su] - 2
@@ -421,7 +496,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         sc.f += df;
         sc.c += cvk - cvo;
         sc.F += (int64_t)phi_den * df + (int64_t)phi_num * (cvk - cvo);
-        ucnt[C_NUPD] += 2u * (old != 0) + 2u * (k != 0);
+        ucnt.nupd += 2u * (old != 0) + 2u * (k != 0);
         // tenure T = L + alpha (|V_0| + |C|) after the move; moving v back to
         // `old` is tabu for T iterations
         const uint32_t mp = (uint32_t)(sc.f + sc.nC);
@@ -432,19 +507,19 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 atomicOr(&ws.bm[v >> 5], 1u << (v & 31));
             else
                 atomicAnd(&ws.bm[v >> 5], ~(1u << (v & 31)));
-            const uint32_t u16 = until < 0xFFFFu ? until : 0xFFFFu;
-            if (u16 > ws.tmax[v]) ws.tmax[v] = (uint16_t)u16;
         }
+        pend_tv = (uint32_t)v;
+        pend_tu = until;
+        if (lane == 0) atomicOr(&ws.dirty[v >> 5], 1u << (v & 31));
         pend_off = lane == 0 ? (uint32_t)v * (uint32_t)TS + position_in(dmask, old) : 0xFFFFFFFFu;
         pend_val = lane == 0 ? until : 0u;
-        ucnt[C_MOVES]++;
         PLSE_WAVE_SYNC();
         if (sc.F < sc.Fbest) {
             sc.Fbest = sc.F;
             sc.fbest = sc.f;
             sc.cbest = sc.c;
             snapshot(I, ws.S, out);
-            ucnt[C_SNAPS]++;
+            ucnt.snaps++;
         }
     }
     if (pend_off != 0xFFFFFFFFu) gptr(tabu)[pend_off] = pend_val;
@@ -456,7 +531,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
 // Greedy conflict removal (Section 3.7): uncolour the vertex with the most
 // conflicts (ties: lowest id) until the colouring is legal.
 __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Scal &sc,
-                       uint64_t *ucnt) {
+                       Cnt &ucnt) {
     const DevInstance &I = a.I;
     const int lane = lane_id();
     const int n = I.n, nv = I.nv, np1 = n + 1;
@@ -486,7 +561,7 @@ __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Sc
             colH[(rc >> 8) * np1 + old] -= 1;
             ws.S[v] = 0;
         }
-        ucnt[C_REPAIRS]++;
+        ucnt.repairs++;
         PLSE_WAVE_SYNC();
     }
     snapshot(I, ws.S, out);
@@ -496,7 +571,7 @@ __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Sc
 }  // namespace
 
 template <int CH>
-__global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
+__global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
     const PlitsArgs a = arg_of<PlitsArgs>(L);
     const int wv = (int)(threadIdx.x >> 6);
@@ -512,20 +587,33 @@ __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     ws.S = base;
     ws.H = base + a.off_h;
     ws.bm = reinterpret_cast<uint32_t *>(base + a.off_bm);
-    ws.tmax = reinterpret_cast<uint16_t *>(base + a.off_tm);
-    ws.elist = reinterpret_cast<uint16_t *>(base + a.off_el);
+    ws.tm8 = base + a.off_tm;
+    ws.dirty = reinterpret_cast<uint32_t *>(base + a.off_dirty);
+    ws.stage = reinterpret_cast<uint16_t *>(base + a.off_el);
     ws.ring = reinterpret_cast<uint32_t *>(base + a.off_ring);
     ws.hk = reinterpret_cast<uint16_t *>(base + a.off_hk);
-    ws.dsz = base + a.off_dsz;
-    for (int v = lane_id(); v < a.I.nv; v += 64) ws.dsz[v] = (uint8_t)(gptr(a.I.vinfo)[v] >> 16);
+    ws.planes = reinterpret_cast<uint32_t *>(base + a.off_planes);
+    ws.nplanes = a.nplanes;
+    {
+        // chunk-count planes: bit b of floor(|D*(v)| / CH) per vertex
+        const int W = (a.I.nv + 31) >> 5;
+        for (int w = lane_id(); w < W; w += 64) {
+            uint32_t pl[6] = {0u, 0u, 0u, 0u, 0u, 0u};
+            const int vend = min(a.I.nv, (w + 1) * 32);
+            for (int v = w * 32; v < vend; ++v) {
+                const uint32_t code = ((gptr(a.I.vinfo)[v] >> 16) & 0xFFu) / CH;
+#pragma unroll
+                for (int b = 0; b < 6; ++b) pl[b] |= ((code >> b) & 1u) << (v & 31);
+            }
+            for (int b = 0; b < a.nplanes; ++b) ws.planes[b * W + w] = pl[b];
+        }
+    }
     const DevInstance &I = a.I;
     uint32_t *tabu = a.tabu + (size_t)ind * I.nv * I.ts;
     const uint8_t *src = a.S_in + (size_t)ind * I.stride;
     uint8_t *out = a.S_out + (size_t)ind * I.stride;
 
-    uint64_t ucnt[kCounters];
-#pragma unroll
-    for (int q = 0; q < kCounters; ++q) ucnt[q] = 0;
+    Cnt ucnt{0u, 0u, 0u, 0u, 0ull, 0ull};
     uint32_t lane_cands = 0;
     Scal sc;
     const uint32_t slot = (uint32_t)readfirst(ind);
@@ -538,15 +626,22 @@ __global__ __launch_bounds__(256) void plits_kernel(const ArgList L) {
     int32_t f_final = sc.fbest;
     if (sc.cbest > 0) {
         repair(a, out, ws, sc, ucnt);
-        f_final = sc.f + (int32_t)ucnt[C_REPAIRS];
+        f_final = sc.f + (int32_t)ucnt.repairs;
     }
-    ucnt[C_CANDS] = wave_sum_u64(lane_cands);
+    const uint64_t cands = wave_sum_u64(lane_cands);
     const int lane = lane_id();
     if (lane < kCounters) {
         uint64_t v = 0;
-#pragma unroll
-        for (int q = 0; q < kCounters; ++q)
-            if (q == lane) v = ucnt[q];
+        switch (lane) {
+            case C_ITERS: v = ucnt.iters; break;
+            case C_MOVES: v = ucnt.iters - ucnt.idle; break;
+            case C_IDLE: v = ucnt.idle; break;
+            case C_CANDS: v = cands; break;
+            case C_ELIG: v = ucnt.elig; break;
+            case C_NUPD: v = ucnt.nupd; break;
+            case C_SNAPS: v = ucnt.snaps; break;
+            default: v = ucnt.repairs; break;
+        }
         gptr(a.cnt_out)[(size_t)ind * kCounters + lane] = v;
     }
     if (lane == 0) gptr(a.f_out)[ind] = f_final;

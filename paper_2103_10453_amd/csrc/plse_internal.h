@@ -34,12 +34,13 @@ struct DevInstance {
     const void *vrec;                // [nv] 32-byte records: D*(v) as a 128-bit colour
                                      //   mask, first slot offset, row | column << 8 |
                                      //   |D*(v)| << 16
-    const uint32_t *vinfo;           // [nv] row | column << 8 | |D*(v)| << 16
+    const uint32_t *vinfo;           // [nv] row | column << 8 | |D*(v)| << 16 | degree << 24
     const uint8_t *cand;             // [nv][ts] moves of v: 0 (uncolour), then D*(v)
                                      //   ascending, zero padding
-    const uint32_t *rowl, *coll;     // [n*n] vertices of row r (column c) at r*n + t:
-                                     //   vertex | (its column (row) << 16)
-    const uint8_t *rowc, *colc;      // [n] vertex counts per row / column
+    int32_t nl, pad2;                // neighbour list length per vertex, 2(n-1)
+    const uint32_t *nbr;             // [nv][nl] the other vertices of v's row, then of
+                                     //   its column: vertex | its other coordinate << 16 |
+                                     //   column flag << 31 (degree entries used)
 };
 
 struct Params {
