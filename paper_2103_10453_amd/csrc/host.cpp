@@ -458,33 +458,68 @@ int launch_ctl(const std::vector<plse_instance *> &hs, bool reset, hipStream_t s
     return PLSE_OK;
 }
 
+// Instances whose PLITS launches share a shape: chunk size and resident
+// waves per CU at their own LDS footprint.  One launch per group (per
+// kMaxLaunch instances) with the group's largest footprint, so a small
+// instance never runs at the occupancy of a large one.
+struct PlitsGroup {
+    int spl = 8, occ = 0, lds = 0, wpb = 1;
+    std::vector<plse_instance *> hs;
+};
+
 // A solve over one or many instances sharing the population size.
 struct Session {
     std::vector<plse_instance *> hs;  // launch order: longest estimated work first
     int p = 0;
     int steps = 0;
-    int wpb = 1, lds_per_wave = 0;
-    hipGraphExec_t ls = nullptr, rest = nullptr;
-    std::vector<hipEvent_t> ev;  // 3 per generation
+    std::vector<PlitsGroup> groups;  // largest estimated work first
+    hipGraphExec_t ls = nullptr, rest = nullptr;  // ls only with a single group
+    std::vector<hipEvent_t> ev;                   // 3 per generation
+    std::vector<hipStream_t> side;                // groups 1.. of a generation
+    std::vector<hipEvent_t> fork;                 // 1 + one per side stream
 
     ~Session() {
         if (ls) (void)hipGraphExecDestroy(ls);
         if (rest) (void)hipGraphExecDestroy(rest);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipStream_t q : side) {
+            (void)hipStreamSynchronize(q);
+            (void)hipStreamDestroy(q);
+        }
+        for (hipEvent_t e : fork) (void)hipEventDestroy(e);
     }
 };
 
+int launch_group(const Session &S, const PlitsGroup &g, hipStream_t s) {
+    return launch_over(g.hs, &ArgBlock::plits, [&](const ArgList &L, int c) {
+        return launch_plits(L, c, S.p, g.lds, g.spl, g.wpb, s);
+    });
+}
+
+// One generation's tabu searches.  Several groups run concurrently: group 0
+// on `s`, the others on side streams forked from and joined back into `s`.
 int enqueue_local_search(Session &S, hipStream_t s) {
     RC_TRY(launch_ctl(S.hs, false, s));
-    for (int spl : {2, 4, 8}) {
-        std::vector<plse_instance *> g;
-        for (plse_instance *h : S.hs)
-            if (choose_spl(h) == spl) g.push_back(h);
-        if (g.empty()) continue;
-        RC_TRY(launch_over(g, &ArgBlock::plits, [&](const ArgList &L, int c) {
-            return launch_plits(L, c, S.p, S.lds_per_wave, spl, S.wpb, s);
-        }));
+    if (S.groups.size() == 1) return launch_group(S, S.groups[0], s);
+    const size_t ns = S.groups.size() - 1;
+    while (S.side.size() < ns) {
+        hipStream_t q = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        S.side.push_back(q);
     }
+    while (S.fork.size() < ns + 1) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        S.fork.push_back(e);
+    }
+    HIP_TRY(hipEventRecord(S.fork[0], s));
+    for (size_t i = 0; i < ns; ++i) {
+        HIP_TRY(hipStreamWaitEvent(S.side[i], S.fork[0], 0));
+        RC_TRY(launch_group(S, S.groups[i + 1], S.side[i]));
+        HIP_TRY(hipEventRecord(S.fork[i + 1], S.side[i]));
+    }
+    RC_TRY(launch_group(S, S.groups[0], s));
+    for (size_t i = 0; i < ns; ++i) HIP_TRY(hipStreamWaitEvent(s, S.fork[i + 1], 0));
     return PLSE_OK;
 }
 
@@ -589,29 +624,42 @@ int admit(const std::vector<plse_instance *> &hs, int p, const uint64_t *seeds, 
     return PLSE_OK;
 }
 
-// Launch order (longest estimated work first) and the shared PLITS shape.
+// Launch order (longest estimated work first) and the PLITS launch groups.
 void shape_session(Session &S) {
     std::stable_sort(S.hs.begin(), S.hs.end(), [](const plse_instance *a, const plse_instance *b) {
         return work_estimate(a) > work_estimate(b);
     });
-    S.lds_per_wave = 0;
-    bool same_wpb = true;
-    std::vector<int> spls;
+    S.groups.clear();
     for (plse_instance *h : S.hs) {
-        S.lds_per_wave = std::max(S.lds_per_wave, plits_lds(h).per_wave);
-        same_wpb = same_wpb && h->wpb == S.hs[0]->wpb;
-        if (std::find(spls.begin(), spls.end(), choose_spl(h)) == spls.end())
-            spls.push_back(choose_spl(h));
+        const int spl = choose_spl(h), per = plits_lds(h).per_wave;
+        const int occ = plits_waves_per_cu(spl, 1, per);
+        auto it = std::find_if(S.groups.begin(), S.groups.end(),
+                               [&](const PlitsGroup &g) { return g.spl == spl && g.occ == occ; });
+        if (it == S.groups.end()) {
+            S.groups.push_back(PlitsGroup{});
+            it = S.groups.end() - 1;
+            it->spl = spl;
+            it->occ = occ;
+        }
+        it->lds = std::max(it->lds, per);
+        it->hs.push_back(h);
     }
-    S.wpb = (same_wpb && S.hs[0]->wpb) ? S.hs[0]->wpb : auto_wpb(S.lds_per_wave, spls);
-    if (S.wpb * S.lds_per_wave > max_lds_per_block()) S.wpb = 1;
+    for (PlitsGroup &g : S.groups) {
+        bool same_wpb = true;
+        for (plse_instance *h : g.hs) same_wpb = same_wpb && h->wpb == g.hs[0]->wpb;
+        g.wpb = (same_wpb && g.hs[0]->wpb) ? g.hs[0]->wpb : auto_wpb(g.lds, {g.spl});
+        if (g.wpb * g.lds > max_lds_per_block()) g.wpb = 1;
+    }
 }
 
 // Upload, initial population P_1 and generation graphs of a session.
 int session_begin(Session &S, const uint64_t *seeds, hipStream_t s) {
     RC_TRY(admit(S.hs, S.p, seeds, s));
     shape_session(S);
-    RC_TRY(capture([&](hipStream_t cs) { return enqueue_local_search(S, cs); }, &S.ls));
+    // a single group's generation is one graph; several groups are enqueued
+    // on forked streams each generation, so they run side by side
+    if (S.groups.size() == 1)
+        RC_TRY(capture([&](hipStream_t cs) { return enqueue_local_search(S, cs); }, &S.ls));
     RC_TRY(capture([&](hipStream_t cs) { return enqueue_rest(S, cs); }, &S.rest));
     S.steps = 0;
     return PLSE_OK;
@@ -627,7 +675,10 @@ int session_step(Session &S, int generations, hipStream_t s) {
     for (int g = 0; g < generations; ++g) {
         const size_t k = 3 * (size_t)(S.steps + g);
         HIP_TRY(hipEventRecord(S.ev[k], s));
-        HIP_TRY(hipGraphLaunch(S.ls, s));
+        if (S.ls)
+            HIP_TRY(hipGraphLaunch(S.ls, s));
+        else
+            RC_TRY(enqueue_local_search(S, s));
         HIP_TRY(hipEventRecord(S.ev[k + 1], s));
         HIP_TRY(hipGraphLaunch(S.rest, s));
         HIP_TRY(hipEventRecord(S.ev[k + 2], s));
@@ -1194,7 +1245,10 @@ struct Request {
     int p = 0, G = 0;
     uint64_t seed = 0;
     size_t off = 0, bytes = 0;
-    int steps = 0;
+    int steps = 0;   // generations finished on the device
+    int queued = 0;  // generations enqueued
+    Session *S = nullptr;       // the request's own session (graphs, events)
+    hipStream_t st = nullptr;   // the request's own stream
     int status = PLSE_PENDING;
     double t_submit = 0, t_admit = -1, t_done = -1;
     std::vector<double> t_gen;  // wall time at the end of each generation
@@ -1252,6 +1306,7 @@ struct plse_server_s {
     size_t budget = 0;
     int max_slots = 1;
     hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on `stream` at creation
     int device = 0;
     std::chrono::steady_clock::time_point t0;
 
@@ -1312,19 +1367,47 @@ struct plse_server_s {
         finished[r->ticket] = r;
     }
 
+    // The request's stream (ordered after work already on the server's
+    // stream) and session: upload, initial population, generation graphs.
+    int start(Request *r) {
+        HIP_TRY(hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking));
+        HIP_TRY(hipStreamWaitEvent(r->st, ready, 0));
+        r->S = new Session();
+        r->S->hs = {r->h};
+        r->S->p = r->p;
+        return session_begin(*r->S, &r->seed, r->st);
+    }
+
+    // Session and stream of a request whose stream has drained.
+    void retire(Request *r) {
+        delete r->S;
+        r->S = nullptr;
+        if (r->st) {
+            (void)hipStreamSynchronize(r->st);
+            (void)hipStreamDestroy(r->st);
+            r->st = nullptr;
+        }
+    }
+
     void loop();
 };
 
+// Admission, then independent progress: every resident request has its own
+// stream and session and keeps up to kAhead generations enqueued, so
+// requests of different sizes overlap on the device and none waits for the
+// generations of another.
 void plse_server_s::loop() {
     (void)hipSetDevice(device);
+    constexpr int kAhead = 2;
     for (;;) {
         std::vector<Request *> fresh;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] { return stop || !waiting.empty() || !resident.empty(); });
+            if (resident.empty())
+                cv.wait(lk, [&] { return stop || !waiting.empty(); });
             if (stop) return;
-            // admission at the generation boundary: arrival order, while the
-            // workspace fits the free arena and a slot is free
+            // admission in arrival order, while the workspace fits the free
+            // arena and a slot is free
             while (!waiting.empty() && (int)(resident.size() + fresh.size()) < max_slots) {
                 Request *r = waiting.front();
                 if (!place(r)) break;
@@ -1334,71 +1417,73 @@ void plse_server_s::loop() {
                 fresh.push_back(r);
             }
         }
-        int rc = PLSE_OK;
-        // new requests: their initial populations, grouped by population size
-        std::map<int, std::vector<Request *>> by_p;
-        for (Request *r : fresh) by_p[r->p].push_back(r);
-        for (auto &kv : by_p) {
-            std::vector<plse_instance *> hs;
-            std::vector<uint64_t> seeds;
-            for (Request *r : kv.second) {
-                hs.push_back(r->h);
-                seeds.push_back(r->seed);
-            }
-            const int e = admit(hs, kv.first, seeds.data(), stream);
-            if (e) {
-                std::lock_guard<std::mutex> lk(mu);
-                for (Request *r : kv.second) finish(r, e);
-                for (Request *r : kv.second) fresh.erase(std::find(fresh.begin(), fresh.end(), r));
-            }
-        }
-        {
+        bool progressed = !fresh.empty();
+        for (Request *r : fresh) {
+            const int e = start(r);
             std::lock_guard<std::mutex> lk(mu);
-            const double t = now();
-            for (Request *r : fresh) {
-                r->t_admit = t;
+            if (e) {
+                retire(r);
+                finish(r, e);
+            } else {
+                r->t_admit = now();
                 resident.push_back(r);
             }
         }
-        // one generation of every resident request, grouped by population size
         std::vector<Request *> run;
         {
             std::lock_guard<std::mutex> lk(mu);
             run = resident;
         }
-        std::map<int, std::vector<plse_instance *>> groups;
-        for (Request *r : run) groups[r->p].push_back(r->h);
-        for (auto &kv : groups) {
-            Session S;
-            S.hs = kv.second;
-            S.p = kv.first;
-            shape_session(S);
-            if (!rc) rc = enqueue_local_search(S, stream);
-            if (!rc) rc = enqueue_rest(S, stream);
-        }
-        if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = PLSE_E_HIP;
-        const double t = now();
-        std::vector<Request *> done;
+        std::vector<std::pair<Request *, int>> done;
         for (Request *r : run) {
-            r->steps += 1;
-            r->t_gen.push_back(t);
-            if (rc || r->steps >= r->G || (r->h->fail_at && r->steps >= r->h->fail_at))
-                done.push_back(r);
+            int rc = PLSE_OK;
+            while (r->steps < r->queued) {
+                const hipError_t q = hipEventQuery(r->S->ev[3 * (size_t)r->steps + 2]);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess) {
+                    rc = hip_fail(q, "hipEventQuery");
+                    break;
+                }
+                r->steps += 1;
+                r->t_gen.push_back(now());
+                progressed = true;
+            }
+            const int fail_at = r->h->fail_at;
+            const bool fault = fail_at && r->steps >= fail_at && r->steps < r->G;
+            if (rc || fault || r->steps >= r->G) {
+                // the request's stream drains before its workspace is released
+                const hipError_t q = hipStreamSynchronize(r->st);
+                if (!rc && q != hipSuccess) rc = hip_fail(q, "hipStreamSynchronize");
+                if (!rc && fault) rc = PLSE_E_FAULT;
+                if (!rc) rc = collect(*r, r->st);
+                done.emplace_back(r, rc);
+                progressed = true;
+                continue;
+            }
+            while (r->queued < r->G && r->queued - r->steps < kAhead &&
+                   !(fail_at && r->queued >= fail_at)) {
+                rc = session_step(*r->S, 1, r->st);
+                if (rc) break;
+                r->queued += 1;
+            }
+            if (rc) {
+                (void)hipStreamSynchronize(r->st);
+                done.emplace_back(r, rc);
+                progressed = true;
+            }
         }
-        std::vector<int> st(done.size(), rc);
-        for (size_t i = 0; i < done.size(); ++i) {
-            if (!rc && done[i]->h->fail_at && done[i]->steps >= done[i]->h->fail_at &&
-                done[i]->steps < done[i]->G)
-                st[i] = PLSE_E_FAULT;
-            else if (!rc)
-                st[i] = collect(*done[i], stream);
-        }
+        for (auto &d : done) retire(d.first);
         {
             std::lock_guard<std::mutex> lk(mu);
-            for (size_t i = 0; i < done.size(); ++i) {
-                resident.erase(std::find(resident.begin(), resident.end(), done[i]));
-                finish(done[i], st[i]);
+            for (auto &d : done) {
+                resident.erase(std::find(resident.begin(), resident.end(), d.first));
+                finish(d.first, d.second);
             }
+        }
+        if (!progressed) {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait_for(lk, std::chrono::microseconds(200),
+                        [&] { return stop || !waiting.empty(); });
         }
     }
 }
@@ -1418,6 +1503,13 @@ int plse_server_create(size_t budget, void *device_ptr, int32_t max_slots, void 
     s->t0 = std::chrono::steady_clock::now();
     s->free_blocks[0] = s->budget;
     set_attributes_once();
+    hipError_t e = hipEventCreateWithFlags(&s->ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(s->ready, s->stream);
+    if (e != hipSuccess) {
+        if (s->ready) (void)hipEventDestroy(s->ready);
+        delete s;
+        return hip_fail(e, "plse_server_create");
+    }
     s->worker = std::thread([s] { s->loop(); });
     *out = s;
     return PLSE_OK;
@@ -1504,11 +1596,13 @@ int plse_server_destroy(plse_server s) {
         delete r;
     }
     for (Request *r : s->resident) {
+        s->retire(r);
         r->h->in_session = false;
         r->h->ws = nullptr;
         delete r;
     }
     for (auto &kv : s->finished) delete kv.second;
+    (void)hipEventDestroy(s->ready);
     delete s;
     return PLSE_OK;
 }
