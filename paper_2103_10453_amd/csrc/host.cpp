@@ -181,14 +181,14 @@ int choose_spl(const plse_instance *h) {
 // the tie values (u16 per colour), bit planes of the chunk counts.
 struct PlitsLds {
     int per_wave, off_h, off_bm, off_tm, off_dirty, off_el, off_ring, off_hk, off_planes;
-    int qmask, nplanes;
+    int nplanes;
 };
 
 PlitsLds plits_lds(const plse_instance *h) {
     PlitsLds L;
     const int W = (h->nv + 31) / 32;
     const int ch = choose_spl(h);
-    const int qcap = next_pow2(63 + 64 * ((h->dmax + ch) / ch));
+    const int qcap = 64 * ((h->dmax + ch) / ch);  // 64 vertices' chunks
     L.off_h = h->stride;
     L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
     L.off_tm = L.off_bm + (int)round_up((size_t)W * 4, 16);
@@ -200,7 +200,6 @@ PlitsLds plits_lds(const plse_instance *h) {
     L.nplanes = 0;
     while ((h->dmax / ch) >> L.nplanes) ++L.nplanes;
     L.per_wave = L.off_planes + (int)round_up((size_t)L.nplanes * W * 4, 16);
-    L.qmask = qcap - 1;
     return L;
 }
 
@@ -355,7 +354,6 @@ PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
     a.off_dirty = pl.off_dirty;
     a.off_planes = pl.off_planes;
     a.nplanes = pl.nplanes;
-    a.qmask = pl.qmask;
     return a;
 }
 
@@ -865,10 +863,14 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
     h->ts = (int)round_up((size_t)h->dmax + 1, 8);
     h->cand.assign((size_t)h->nv * h->ts, 0);
     for (int v = 0; v < h->nv; ++v) {
+        // the last domain colour repeats to the end of the row: a repeated
+        // position evaluates exactly as that colour's own, so the search
+        // needs no test for positions past the domain
         uint8_t *row = &h->cand[(size_t)v * h->ts];
         int t = 1;
         for (int k = 1; k <= n; ++k)
             if ((dmask[2 * v + (k >> 6)] >> (k & 63)) & 1ull) row[t++] = (uint8_t)k;
+        for (int q = t; q < h->ts; ++q) row[q] = row[t - 1];
     }
     h->stride = (int)round_up((size_t)std::max(h->nv, 1), 16);
     // defaults: Table 1 and Section 3.3, total depth 10 n^2

@@ -210,7 +210,6 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     const int32_t phi_num = (phase == 1) ? 1 : nv;
     const int32_t phi_den = (phase == 1) ? 2 : 1;
     const uint32_t tag = (phase == 1) ? TAG_PLITS1 : TAG_PLITS2;
-    const uint32_t qmask = (uint32_t)a.qmask;
     // Move values on a 16-bit scale e ordered like delta: e = delta when the
     // phase's values fit (phase 1, and phase 2 with |V| <= 64); otherwise
     // e = 4 dc + df, which orders moves as |V| dc + df does since |df| <= 1
@@ -275,8 +274,8 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         const uint32_t w2 = readlane_u32(wz, (int)(itu & 63u));
         // colour halves of the tie values (written first: independent of the
         // eligibility scan, which covers their latency)
-#pragma unroll 1
-        for (int k = lane; k <= n; k += 64) ws.hk[k] = (uint16_t)(fmix32(w2 ^ (uint32_t)k) >> 16);
+        if (lane <= n) ws.hk[lane] = (uint16_t)(fmix32(w2 ^ (uint32_t)lane) >> 16);
+        if (lane + 64 <= n) ws.hk[lane + 64] = (uint16_t)(fmix32(w2 ^ (uint32_t)(lane + 64)) >> 16);
         // 1. eligible vertices (ascending rank over the bitmap): their number
         //    m, and the first 64 of them staged for dealing
         uint32_t m = 0;
@@ -316,9 +315,10 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         if (pend_off != 0xFFFFFFFFu) gptr(tabu)[pend_off] = pend_val;
         uint32_t head = 0u, tail = 0u, g = 0u;
         for (;;) {
-            // deal the rows of the next 64 eligible vertices while fewer than
-            // a round of chunks is pending
-            while (tail - head < 64u && g < m) {
+            // once the ring is empty, deal the rows of the next 64 eligible
+            // vertices into it
+            if (head == tail && g < m) {
+                head = tail = 0u;
                 if (g > 0) {
                     // stage eligible vertices of rank g .. g+63 (the bitmap
                     // does not change within the iteration)
@@ -354,7 +354,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 uint32_t total;
                 const uint32_t at = tail + wave_excl_scan_dpp(nch, &total);
 #pragma unroll 1
-                for (uint32_t t = 0; t < nch; ++t) ws.ring[(at + t) & qmask] = v | (t << 16);
+                for (uint32_t t = 0; t < nch; ++t) ws.ring[at + t] = v | (t << 16);
                 tail += total;
                 g += 64u;
                 PLSE_WAVE_SYNC();
@@ -363,7 +363,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             const uint32_t x = head + (uint32_t)lane;
             head = min(head + 64u, tail);
             if (x < tail) {
-                const uint32_t ent = ws.ring[x & qmask];
+                const uint32_t ent = ws.ring[x];
                 const int v = (int)(ent & 0xFFFFu);
                 const int p0 = (int)(ent >> 16) * CH;
                 const int s = ws.S[v];
@@ -376,7 +376,6 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 for (int t = 0; t < CH; ++t) tv[t] = 0u;
                 if (live) Chunk<CH>::tabu(tabu + (size_t)v * TS + p0, tv);
                 const int r = (int)(vi & 0xFFu), c = (int)((vi >> 8) & 0xFFu);
-                const int lim = (int)((vi >> 16) & 0xFFu) - p0;  // positions t <= lim exist
                 if (p0 == 0) lane_cands += (vi >> 16) & 0xFFu;
                 const uint8_t *rH = rowH + r * np1;
                 const uint8_t *cH = colH + c * np1;
@@ -403,7 +402,10 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                     const int k = kk[t];
                     const int32_t b = (t == 0 && p0 == 0) ? base + eB : base;
                     const int32_t eb = eA * cnt[t] + b;
-                    const bool ok = (t <= lim) && (k != s) && (itu >= tv[t] || eb < teb);
+                    // positions past the domain repeat its last colour and
+                    // that colour's tabu entry: they never beat the original,
+                    // which this lane met first
+                    const bool ok = (k != s) && (itu >= tv[t] || eb < teb);
                     const uint32_t hi = ((uint32_t)eb << 16) | (hv ^ hkv[t]);
                     const bool take = ok && hi < lhi;
                     lhi = take ? hi : lhi;
@@ -511,8 +513,17 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         pend_tv = (uint32_t)v;
         pend_tu = until;
         if (lane == 0) atomicOr(&ws.dirty[v >> 5], 1u << (v & 31));
-        pend_off = lane == 0 ? (uint32_t)v * (uint32_t)TS + position_in(dmask, old) : 0xFFFFFFFFu;
-        pend_val = lane == 0 ? until : 0u;
+        {
+            // the entry of the last domain colour is repeated over the rest
+            // of its chunk, where the candidate row repeats that colour
+            const uint32_t po = position_in(dmask, old);
+            const uint32_t dv = (uint32_t)(__popcll(((uint64_t)dmask.y << 32) | dmask.x) +
+                                           __popcll(((uint64_t)dmask.w << 32) | dmask.z));
+            const uint32_t nrep = po == dv ? (uint32_t)CH - dv % (uint32_t)CH : 1u;
+            pend_off = (uint32_t)lane < nrep ? (uint32_t)v * (uint32_t)TS + po + (uint32_t)lane
+                                             : 0xFFFFFFFFu;
+            pend_val = until;
+        }
         PLSE_WAVE_SYNC();
         if (sc.F < sc.Fbest) {
             sc.Fbest = sc.F;

@@ -49,7 +49,6 @@ struct PlitsArgs {
     int32_t lds_per_wave;
     int32_t off_h, off_bm, off_tm, off_dirty, off_el, off_ring, off_hk, off_planes;
     int32_t nplanes;       // bit planes of floor(|D*(v)| / CH), at most 6
-    int32_t qmask;         // ring capacity - 1 (a power of two)
 };
 
 struct InitArgs {
