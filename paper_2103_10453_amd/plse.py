@@ -302,12 +302,16 @@ class Solver:
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
+            self.h = None
+            # at interpreter shutdown the module globals may already be gone
             try:
                 plse_attach_workspace(h, None)
             except Exception:
                 pass
-            plse_destroy(h)
-            self.h = None
+            try:
+                plse_destroy(h)
+            except Exception:
+                pass
 
     def set_param(self, key, value):
         plse_set_param(self.h, key, value)
