@@ -36,7 +36,7 @@ struct DevInstance {
                                      //   |D*(v)| << 16
     const uint32_t *vinfo;           // [nv] row | column << 8 | |D*(v)| << 16 | degree << 24
     const uint8_t *cand;             // [nv][ts] moves of v: 0 (uncolour), then D*(v)
-                                     //   ascending, zero padding
+                                     //   ascending; the last colour repeats to ts
     int32_t nl, pad2;                // neighbour list length per vertex, 2(n-1)
     const uint32_t *nbr;             // [nv][nl] the other vertices of v's row, then of
                                      //   its column: vertex | its other coordinate << 16 |
