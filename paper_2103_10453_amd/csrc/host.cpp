@@ -180,7 +180,7 @@ int choose_spl(const plse_instance *h) {
 // group of 64 vertices dealt while under 64 are pending), colour halves of
 // the tie values (u16 per colour), bit planes of the chunk counts.
 struct PlitsLds {
-    int per_wave, off_h, off_bm, off_tm, off_dirty, off_el, off_ring, off_hk, off_planes;
+    int per_wave, off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_planes;
     int nplanes;
 };
 
@@ -192,8 +192,7 @@ PlitsLds plits_lds(const plse_instance *h) {
     L.off_h = h->stride;
     L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
     L.off_tm = L.off_bm + (int)round_up((size_t)W * 4, 16);
-    L.off_dirty = L.off_tm + (int)round_up((size_t)h->nv, 16);
-    L.off_el = L.off_dirty + (int)round_up((size_t)W * 4, 16);
+    L.off_el = L.off_tm + (int)round_up((size_t)h->nv, 16);
     L.off_ring = L.off_el + 128;
     L.off_hk = L.off_ring + qcap * 4;
     L.off_planes = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
@@ -351,7 +350,6 @@ PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
     a.off_el = pl.off_el;
     a.off_ring = pl.off_ring;
     a.off_hk = pl.off_hk;
-    a.off_dirty = pl.off_dirty;
     a.off_planes = pl.off_planes;
     a.nplanes = pl.nplanes;
     return a;

@@ -19,12 +19,12 @@
 // the domain sizes are.
 //
 // Per wave (LDS): S[stride] colours, rowcnt|colcnt, the eligibility bitmap of
-//   V_0 u C(S), tm8[|V|] (latest tabu expiry written per vertex, relative to
-//   a base advanced by 128 iterations at a time, 255 = "treat as live"; a
-//   vertex not live has no tabu move), a bitmap of vertices with tabu entries
-//   this phase, the 64 eligible vertices being dealt, a ring of chunk
-//   descriptors, the colour halves of the iteration's tie values and bit
-//   planes of the vertices' chunk counts.
+//   V_0 u C(S), tm8[|V|] (per vertex: whether this phase wrote its tabu row,
+//   and its latest tabu expiry relative to a base advanced by 128 iterations
+//   at a time, 255 = "treat as live"; a vertex not live has no tabu move),
+//   the 64 eligible vertices being dealt, a ring of chunk descriptors, the
+//   colour halves of the iteration's tie values and bit planes of the
+//   vertices' chunk counts.
 // Per individual (HBM): tabu[|V|][TS] "allowed from" iteration of every move,
 //   read only for vertices with a live entry; all zero between phases (each
 //   phase clears the rows it wrote).
@@ -36,8 +36,9 @@
 //      best key per lane: (value, tie value) above the move id v (n+1) + k,
 //      the tie value being the top half of fmix32(w1 ^ v) ^ fmix32(w2 ^ k)
 //      for the iteration's random words w1, w2;
-//   3. two DPP wave minima (key halves) pick the unique best admissible move,
-//      whose id names it;
+//   3. a DPP wave minimum of the upper key words, then (only when several
+//      lanes hold it) of their move ids, picks the unique best admissible
+//      move;
 //   4. counts, colour, eligibility bits of the row/column vertices holding the
 //      old or new colour, tenure, tabu entry, best-solution snapshot.
 #include "device_common.h"
@@ -51,8 +52,8 @@ struct WaveState {
     uint8_t *S;
     uint8_t *H;        // rowcnt [n][n+1] then colcnt [n][n+1]
     uint32_t *bm;
-    uint8_t *tm8;      // [|V|] tabu expiry relative to the base (0: none, 255: sticky)
-    uint32_t *dirty;   // [W] vertices with tabu entries written this phase
+    uint8_t *tm8;      // [|V|] 0: no tabu entry this phase; 1: entries, all expired;
+                       // m in 2..254: latest expiry = base + m - 1; 255: treat as live
     uint16_t *stage;   // [64] the eligible vertices being dealt
     uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16
     uint16_t *hk;      // [n+1] colour halves of the iteration's tie values
@@ -127,7 +128,6 @@ __device__ void setup_state(const DevInstance &I, const uint8_t *src, const Wave
         ws.bm[w] = bits;
     }
     for (int q = lane; q < (nv + 3) >> 2; q += 64) reinterpret_cast<uint32_t *>(ws.tm8)[q] = 0u;
-    for (int w = lane; w < W; w += 64) ws.dirty[w] = 0u;
     PLSE_WAVE_SYNC();
     sc.f = (int32_t)wave_sum_u32_dpp(f);
     sc.c = (int32_t)(wave_sum_u32_dpp(c2) >> 1);  // each conflicting edge seen twice
@@ -139,11 +139,11 @@ __device__ __forceinline__ void snapshot(const DevInstance &I, const uint8_t *S,
         gstore4(reinterpret_cast<u32x4 *>(dst) + q, reinterpret_cast<const u32x4 *>(S)[q]);
 }
 
-// Zero the tabu rows this phase wrote.
+// Zero the tabu rows this phase wrote (vertices with a nonzero mark).
 __device__ void clear_tabu(const DevInstance &I, uint32_t *tabu, const WaveState &ws) {
     const int q4 = I.ts >> 2;
     for (int v = lane_id(); v < I.nv; v += 64) {
-        if ((ws.dirty[v >> 5] >> (v & 31)) & 1u) {
+        if (ws.tm8[v] != 0) {
             u32x4 *tb = reinterpret_cast<u32x4 *>(tabu + (size_t)v * I.ts);
             for (int t = 0; t < q4; ++t) gstore4(tb + t, u32x4{0u, 0u, 0u, 0u});
         }
@@ -238,6 +238,9 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
     // the next iteration (under the eligibility scan)
     uint32_t pend_tv = 0xFFFFFFFFu, pend_tu = 0u;
     uint32_t tbase = 0u;  // base of the relative expiry marks
+    // lane roles of the count updates (all ones / all zeros)
+    const uint32_t ln_new = lane >= 2 ? 0xFFFFFFFFu : 0u;  // entering colour
+    const uint32_t ln_odd = (lane & 1) ? 0xFFFFFFFFu : 0u;  // column count
     PLSE_WAVE_SYNC();
 
     for (int64_t it = 0; it < iters; ++it) {
@@ -249,7 +252,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             wz = rw.z;
         }
         if ((itu & 127u) == 0u && itu != 0u) {
-            // advance the base: marks drop by 128 (expired ones to 0), 255 stays
+            // advance the base: marks drop by 128 (expired ones to 1), 255 stays
             tbase += 128u;
             PLSE_WAVE_SYNC();
             for (int q = lane; q < (nv + 3) >> 2; q += 64) {
@@ -258,15 +261,15 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const uint32_t b = (x >> (8 * t)) & 0xFFu;
-                    y |= (b == 255u ? 255u : (b > 128u ? b - 128u : 0u)) << (8 * t);
+                    y |= (b == 255u ? 255u : (b > 128u ? b - 128u : (b != 0u ? 1u : 0u))) << (8 * t);
                 }
                 reinterpret_cast<uint32_t *>(ws.tm8)[q] = y;
             }
             PLSE_WAVE_SYNC();
         }
         if (lane == 0 && pend_tv != 0xFFFFFFFFu) {
-            const uint32_t rel = pend_tu - tbase;  // >= 1
-            const uint32_t mark = rel > 254u ? 255u : rel;
+            const uint32_t rel = pend_tu - tbase;  // >= 0
+            const uint32_t mark = rel > 253u ? 255u : rel + 1u;
             if (mark > ws.tm8[pend_tv]) ws.tm8[pend_tv] = (uint8_t)mark;
         }
         const uint32_t w0 = readlane_u32(wx, (int)(itu & 63u));
@@ -368,7 +371,7 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
                 const int p0 = (int)(ent >> 16) * CH;
                 const int s = ws.S[v];
                 const uint32_t tm = ws.tm8[v];
-                const bool live = tm == 255u || tm > itu - tbase;
+                const bool live = tm == 255u || tm > itu - tbase + 1u;
                 const uint32_t vi = gptr(I.vinfo)[v];
                 const auto cw = Chunk<CH>::colours(I.cand + (size_t)v * TS + p0);
                 uint32_t tv[CH];
@@ -440,59 +443,56 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         const int c = (int)((pay >> 8) & 0xFFu);
         const int old = (int)((pay >> 16) & 0xFFu);
         const int deg = (int)(pay >> 24);
-        // memory the apply needs, fetched together up front: v's domain mask
-        // (tabu position of the colour it leaves) and its first 64 neighbours
-        const u32x4 dmask = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
-        const uint32_t *nb = I.nbr + (size_t)v * I.nl;
-        const uint32_t ent0 = lane < deg ? gptr(nb)[lane] : 0u;
+        // the counts of the two colours in v's row and column, then the memory
+        // the apply needs, fetched together: v's first 64 neighbours and its
+        // domain mask (the tabu position of the colour it leaves)
         uint8_t *rH = rowH + r * np1;
         uint8_t *cH = colH + c * np1;
-        const int32_t cvk = k ? ((int32_t)rH[k] + (int32_t)cH[k]) : 0;
-        const int32_t cvo = old ? ((int32_t)rH[old] + (int32_t)cH[old] - 2) : 0;
+        const int32_t hk_r = rH[k], hk_c = cH[k], ho_r = rH[old], ho_c = cH[old];
+        const uint32_t *nb = I.nbr + (size_t)v * I.nl;
+        const uint32_t ent0 = lane < deg ? gptr(nb)[lane] : 0u;
+        const u32x4 dmask = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
+        const int32_t cvk = k ? hk_r + hk_c : 0;
+        const int32_t cvo = old ? ho_r + ho_c - 2 : 0;
+        const bool vC = (k != 0) && (cvk > 0);
         PLSE_WAVE_SYNC();
-        // 4. apply: counts (lanes 0-3, byte-packed LDS atomics, no carries:
-        //    counts stay within 0..n) and colour (lane 4)
-        if (lane < 4 && (lane < 2 ? old != 0 : k != 0)) {
-            const int col = lane < 2 ? old : k;
-            const int byte = (int)(((lane & 1) ? cH : rH) - ws.H) + col;
-            uint32_t *w = reinterpret_cast<uint32_t *>(ws.H) + (byte >> 2);
-            const uint32_t one = 1u << ((byte & 3) * 8);
-            if (lane < 2)
-                atomicSub(w, one);
-            else
-                atomicAdd(w, one);
+        // 4. apply.  Counts: lanes 0-1 the leaving colour's row and column
+        //    count (-1), lanes 2-3 the entering colour's (+1), as LDS adds on
+        //    the bytes of u32 words (exact: counts stay within 0..n, nothing
+        //    carries), an add of 0 for colour 0.  Lane 0: v's colour, and v's
+        //    eligibility bit cleared (an exact add: v was eligible) unless v
+        //    stays in V_0 u C.  Lane roles are bit masks, not branches.
+        if (lane < 4) {
+            const uint32_t col = (ln_new & (uint32_t)k) | (~ln_new & (uint32_t)old);
+            const uint32_t hb = ((ln_odd & (uint32_t)(cH - ws.H)) |
+                                 (~ln_odd & (uint32_t)(rH - ws.H))) + col;
+            const uint32_t add = col != 0u ? ((ln_new & 2u) - 1u) << ((hb & 3u) * 8u) : 0u;
+            atomicAdd(reinterpret_cast<uint32_t *>(ws.H) + (hb >> 2), add);
         }
-        if (lane == 4) ws.S[v] = (uint8_t)k;
+        if (lane == 0) {
+            ws.S[v] = (uint8_t)k;
+            atomicAdd(&ws.bm[v >> 5], (k == 0 || vC) ? 0u : 0u - (1u << (v & 31)));
+        }
         PLSE_WAVE_SYNC();
-        // eligibility of the row/column vertices holding the old or new colour
+        // eligibility of the row/column vertices holding the old or new colour:
+        // all reads unconditional, one toggle where it changes
         int32_t dC = 0;
         for (int t0 = 0; t0 < deg; t0 += 64) {
             const int t = t0 + lane;
-            bool enter = false, leave = false;
-            if (t < deg) {
-                const uint32_t ent = t0 == 0 ? ent0 : gptr(nb)[t];
-                const bool inrow = (ent >> 31) == 0;
-                const int u = (int)(ent & 0xFFFFu), other = (int)((ent >> 16) & 0x7FFFu);
-                {
-                    const int su = ws.S[u];
-                    if (su != 0 && (su == old || su == k)) {
-                        const int cu = inrow ? (int)rH[su] + (int)colH[other * np1 + su] - 2
-                                             : (int)rowH[other * np1 + su] + (int)cH[su] - 2;
-                        const bool was = (ws.bm[u >> 5] >> (u & 31)) & 1u;
-                        const bool now = cu > 0;
-                        if (now && !was) {
-                            enter = true;
-                            atomicOr(&ws.bm[u >> 5], 1u << (u & 31));
-                        } else if (!now && was) {
-                            leave = true;
-                            atomicAnd(&ws.bm[u >> 5], ~(1u << (u & 31)));
-                        }
-                    }
-                }
-            }
-            dC += (int32_t)__popcll(ballot(enter)) - (int32_t)__popcll(ballot(leave));
+            const uint32_t ent = t0 == 0 ? ent0 : (t < deg ? gptr(nb)[t] : 0u);
+            const bool inrow = (ent >> 31) == 0;
+            const int u = (int)(ent & 0xFFFFu), other = (int)((ent >> 16) & 0x7FFFu);
+            const int su = ws.S[u];
+            const uint32_t bw = ws.bm[u >> 5];
+            const int rrow = inrow ? r : other, rcol = inrow ? other : c;
+            const int cu = (int)rowH[rrow * np1 + su] + (int)colH[rcol * np1 + su] - 2;
+            const bool hit = t < deg && su != 0 && (su == old || su == k);
+            const bool was = (bw >> (u & 31)) & 1u;
+            const bool now = cu > 0;
+            const bool flip = hit && (now != was);
+            if (flip) atomicXor(&ws.bm[u >> 5], 1u << (u & 31));
+            dC += (int32_t)__popcll(ballot(flip && now)) - (int32_t)__popcll(ballot(flip && !now));
         }
-        const bool vC = (k != 0) && (cvk > 0);
         const int32_t df = (k == 0 ? 1 : 0) - (old == 0 ? 1 : 0);
         sc.nC += dC + (vC ? 1 : 0) - (old ? 1 : 0);
         sc.f += df;
@@ -504,15 +504,8 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         const uint32_t mp = (uint32_t)(sc.f + sc.nC);
         const uint32_t T = scale32(w0, 10u) + udiv_by(alpha_n * mp, alpha_d, m_alpha);
         const uint32_t until = itu + 1u + T;
-        if (lane == 0) {
-            if (k == 0 || vC)
-                atomicOr(&ws.bm[v >> 5], 1u << (v & 31));
-            else
-                atomicAnd(&ws.bm[v >> 5], ~(1u << (v & 31)));
-        }
         pend_tv = (uint32_t)v;
         pend_tu = until;
-        if (lane == 0) atomicOr(&ws.dirty[v >> 5], 1u << (v & 31));
         {
             // the entry of the last domain colour is repeated over the rest
             // of its chunk, where the candidate row repeats that colour
@@ -533,7 +526,10 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
             ucnt.snaps++;
         }
     }
+    // the last move's tabu entry and mark: the mark tells clear_tabu the row
+    // was written
     if (pend_off != 0xFFFFFFFFu) gptr(tabu)[pend_off] = pend_val;
+    if (lane == 0 && pend_tv != 0xFFFFFFFFu && ws.tm8[pend_tv] == 0) ws.tm8[pend_tv] = 1;
     PLSE_WAVE_SYNC();
     clear_tabu(I, tabu, ws);
     PLSE_WAVE_SYNC();
@@ -599,7 +595,6 @@ __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     ws.H = base + a.off_h;
     ws.bm = reinterpret_cast<uint32_t *>(base + a.off_bm);
     ws.tm8 = base + a.off_tm;
-    ws.dirty = reinterpret_cast<uint32_t *>(base + a.off_dirty);
     ws.stage = reinterpret_cast<uint16_t *>(base + a.off_el);
     ws.ring = reinterpret_cast<uint32_t *>(base + a.off_ring);
     ws.hk = reinterpret_cast<uint16_t *>(base + a.off_hk);

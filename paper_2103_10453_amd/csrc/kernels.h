@@ -47,7 +47,7 @@ struct PlitsArgs {
     int32_t p;
     uint32_t seed_lo, seed_hi;
     int32_t lds_per_wave;
-    int32_t off_h, off_bm, off_tm, off_dirty, off_el, off_ring, off_hk, off_planes;
+    int32_t off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_planes;
     int32_t nplanes;       // bit planes of floor(|D*(v)| / CH), at most 6
 };
 
