@@ -165,8 +165,8 @@ __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
             uint32_t va = 0u, vb = 0u;
             if (wc < nw) {
                 const int ra = r0 + row, rb = c0 + row;
-                if (ra < a.m) va = a.planes[((size_t)ra * a.W + w0) * B + rem];
-                if (rb < a.m) vb = a.planes[((size_t)rb * a.W + w0) * B + rem];
+                if (ra < a.m) va = *gptr(a.planes + ((size_t)ra * a.W + w0) * B + rem);
+                if (rb < a.m) vb = *gptr(a.planes + ((size_t)rb * a.W + w0) * B + rem);
             }
             As[row * PITCH + rem] = va;
             Bs[row * PITCH + rem] = vb;
@@ -185,9 +185,12 @@ __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    uint32_t x = 0u;
+                    // OR over planes of the XOR: one 3-input op per plane
+                    // (v_bitop3 with table 0xBE = (s0 ^ s1) | s2)
+                    uint32_t x = ra[i][0] ^ rb[j][0];
 #pragma unroll
-                    for (int b = 0; b < B; ++b) x |= ra[i][b] ^ rb[j][b];
+                    for (int b = 1; b < B; ++b)
+                        x = __builtin_amdgcn_bitop3_b32(ra[i][b], rb[j][b], x, 0xBE);
                     acc[i][j] += (uint32_t)__popc(x);
                 }
         }
@@ -202,13 +205,13 @@ __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
     for (int q = tid; q < kTile * kTile; q += 256) {
         const int row = q >> 6, col = q & 63;
         const int gr = r0 + row, gc = c0 + col;
-        if (gr < a.m && gc < a.m) a.D[(size_t)gr * a.ld + gc] = Dt[row][col];
+        if (gr < a.m && gc < a.m) *gptr(a.D + (size_t)gr * a.ld + gc) = Dt[row][col];
     }
     if (I != J) {
         for (int q = tid; q < kTile * kTile; q += 256) {
             const int row = q >> 6, col = q & 63;  // mirror: D[c0 + row][r0 + col]
             const int gr = c0 + row, gc = r0 + col;
-            if (gr < a.m && gc < a.m) a.D[(size_t)gr * a.ld + gc] = Dt[col][row];
+            if (gr < a.m && gc < a.m) *gptr(a.D + (size_t)gr * a.ld + gc) = Dt[col][row];
         }
     }
 }
@@ -342,8 +345,10 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     const int nbw = (m + 31) / 32;
     // keys in LDS: generated and sorted here; else already sorted in global
     // memory by select_keys_kernel / sort_*_kernel
-    uint64_t *K = a.keys_in_lds ? reinterpret_cast<uint64_t *>(lds + ((nbw * 4 + 15) & ~15))
-                                : a.keys_g;
+    const int off_keys = (nbw * 4 + 15) & ~15;
+    uint64_t *K = a.keys_in_lds ? reinterpret_cast<uint64_t *>(lds + off_keys) : a.keys_g;
+    // close lists of the 64 candidates being scanned, staged per block
+    uint16_t *adjs = reinterpret_cast<uint16_t *>(lds + off_keys + (a.keys_in_lds ? P2 * 8 : 0));
     if (a.keys_in_lds)
         for (int q = tid; q < (P2 >> 2); q += nthr) select_keys(a, (uint32_t)gen, q, K);
     for (int q = tid; q < nbw; q += nthr) blocked[q] = 0u;
@@ -371,8 +376,15 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     for (int base = 0; base < m && !full; base += 64) {
         const int r = base + lane;
         const bool valid = r < m;
-        const int x = valid ? (int)(K[r] & 0xFFFFull) : 0;
-        const int d = valid ? a.deg[x] : 0;
+        const uint64_t kr = !valid ? 0ull : (a.keys_in_lds ? K[r] : *gptr(a.keys_g + r));
+        const int x = (int)(kr & 0xFFFFull);
+        const int d = valid ? *gptr(a.deg + x) : 0;
+        if (d > 0 && d <= kAdj) {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(a.adj + (size_t)x * kAdj);
+            u32x4 *dst = reinterpret_cast<u32x4 *>(adjs + lane * kAdj);
+            for (int q = 0; q < (d + 7) / 8; ++q) dst[q] = gload4(src + q);
+        }
+        PLSE_WAVE_SYNC();
         int pos = 0;
         while (pos < 64) {
             const bool blk = valid && ((blocked[x >> 5] >> (x & 31)) & 1u);
@@ -383,9 +395,9 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
             const uint64_t accm = ballot(inr && !blk), rejm = ballot(inr && blk);
             const int room = a.p - na;
             const uint32_t ra = rank_below(accm);
-            if (inr && !blk && (int)ra < room) a.acc[na + (int)ra] = x;
+            if (inr && !blk && (int)ra < room) *gptr(a.acc + na + (int)ra) = x;
             const uint32_t rr = rank_below(rejm);
-            if (inr && blk) a.rej[nr + (int)rr] = x;
+            if (inr && blk) *gptr(a.rej + nr + (int)rr) = x;
             const int nacc = (int)__popcll(accm);
             na += nacc < room ? nacc : room;
             nr += (int)__popcll(rejm);
@@ -395,7 +407,7 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
             }
             if (L == 64) break;
             const int xL = (int)shfl_u32((uint32_t)x, L), dL = (int)shfl_u32((uint32_t)d, L);
-            if (lane == 0) a.acc[na] = xL;
+            if (lane == 0) *gptr(a.acc + na) = xL;
             ++na;
             if (na >= a.p) {
                 full = true;
@@ -403,13 +415,13 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
             }
             if (dL <= kAdj) {
                 if (lane < dL) {
-                    const int y = a.adj[(size_t)xL * kAdj + lane];
+                    const int y = adjs[L * kAdj + lane];
                     atomicOr(&blocked[y >> 5], 1u << (y & 31));
                 }
             } else {
                 const int16_t *row = a.D + (size_t)xL * a.ld;
                 for (int y = lane; y < m; y += 64)
-                    if (y != xL && a.spacing * (int64_t)row[y] <= (int64_t)a.nv)
+                    if (y != xL && a.spacing * (int64_t)*gptr(row + y) <= (int64_t)a.nv)
                         atomicOr(&blocked[y >> 5], 1u << (y & 31));
             }
             PLSE_WAVE_SYNC();
@@ -418,12 +430,12 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     }
     // fill rule: rejected candidates in scan order complete a short population
     PLSE_WAVE_SYNC();
-    for (int t = lane; t < a.p - na; t += 64) a.acc[na + t] = a.rej[t];
+    for (int t = lane; t < a.p - na; t += 64) *gptr(a.acc + na + t) = *gptr(a.rej + t);
 }
 
 size_t select_lds_bytes(int m, int pow2, bool keys_in_lds) {
     const size_t b = ((size_t)((m + 31) / 32) * 4 + 15) & ~(size_t)15;
-    return b + (keys_in_lds ? (size_t)pow2 * 8 : 0);
+    return b + (keys_in_lds ? (size_t)pow2 * 8 : 0) + (size_t)64 * kAdj * 2;
 }
 
 
@@ -520,15 +532,15 @@ __global__ __launch_bounds__(256) void match_kernel(const ArgList L) {
     if (i >= a.p) return;
     for (int q = lane; q < nbw; q += 64) excl[q] = 0u;
     PLSE_WAVE_SYNC();
-    const int hcount = max(a.hc[i], 0);
+    const int hcount = max(*gptr(a.hc + i), 0);
     const int nh = min(hcount, a.hist_len);
     for (int t = lane; t < nh; t += 64) {
-        const uint64_t u = a.hist[(size_t)i * kHist + t];
+        const uint64_t u = *gptr(a.hist + (size_t)i * kHist + t);
         uint32_t h = hash_uid(u) & (uint32_t)(a.hsize - 1);
         for (;;) {
-            const uint64_t k = a.hkeys[h];
+            const uint64_t k = *gptr(a.hkeys + h);
             if (k == u) {
-                const int s = a.hvals[h];
+                const int s = *gptr(a.hvals + h);
                 atomicOr(&excl[s >> 5], 1u << (s & 31));
                 break;
             }
@@ -537,17 +549,30 @@ __global__ __launch_bounds__(256) void match_kernel(const ArgList L) {
         }
     }
     PLSE_WAVE_SYNC();
-    const int ai = a.idx ? a.idx[i] : i;
+    const int ai = a.idx ? *gptr(a.idx + i) : i;
     const int16_t *row = a.D + (size_t)ai * a.ld;
     uint64_t best = ~0ull;
     for (int pass = 0; pass < 2 && best == ~0ull; ++pass) {
+        // branch-free body, unrolled: several index and distance loads in
+        // flight per lane
         uint64_t lb = ~0ull;
-        for (int j = lane; j < a.p; j += 64) {
-            if (j == i) continue;
-            if (pass == 0 && ((excl[j >> 5] >> (j & 31)) & 1u)) continue;
-            const int aj = a.idx ? a.idx[j] : j;
-            const uint64_t key = ((uint64_t)(uint16_t)row[aj] << 32) | (uint32_t)j;
-            lb = key < lb ? key : lb;
+        if (a.idx) {
+#pragma unroll 8
+            for (int j = lane; j < a.p; j += 64) {
+                const int aj = *gptr(a.idx + j);
+                const uint32_t d = (uint16_t)*gptr(row + aj);
+                const bool ok = j != i && (pass != 0 || !((excl[j >> 5] >> (j & 31)) & 1u));
+                const uint64_t key = ok ? (((uint64_t)d << 32) | (uint32_t)j) : ~0ull;
+                lb = key < lb ? key : lb;
+            }
+        } else {
+#pragma unroll 8
+            for (int j = lane; j < a.p; j += 64) {
+                const uint32_t d = (uint16_t)*gptr(row + j);
+                const bool ok = j != i && (pass != 0 || !((excl[j >> 5] >> (j & 31)) & 1u));
+                const uint64_t key = ok ? (((uint64_t)d << 32) | (uint32_t)j) : ~0ull;
+                lb = key < lb ? key : lb;
+            }
         }
         best = wave_min_u64(lb);
     }
