@@ -47,7 +47,7 @@ struct Layout {
     size_t vrc, vrec, cand, vinfo, nbr;
     size_t args, ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
-    size_t tabu, planes, D, deg, adj, keys, rej, acc, hkeys, hvals, partner, dpart;
+    size_t tabu, planes, D, deg, adj, keys, rej, acc, pos, hkeys, hvals, partner, dpart;
     size_t total;
     int pow2_sel, hsize;
 };
@@ -265,6 +265,7 @@ Layout plan(const plse_instance *h, int p) {
     L.keys = take(8 * (size_t)L.pow2_sel);
     L.rej = take(4 * m);
     L.acc = take(4 * (size_t)p);
+    L.pos = take(4 * m);
     L.hsize = next_pow2(std::max<int>(4, (int)m));
     L.hkeys = take(8 * (size_t)L.hsize);
     L.hvals = take(4 * (size_t)L.hsize);
@@ -367,6 +368,7 @@ SelectArgs make_select(plse_instance *h, int p, int gen_fixed, uint64_t seed, co
     a.keys_g = at<uint64_t>(h, L.keys);
     a.rej = at<int32_t>(h, L.rej);
     a.acc = acc;
+    a.pos = at<int32_t>(h, L.pos);
     a.p = p;
     a.m = 2 * p;
     a.ld = ld;
@@ -417,13 +419,15 @@ void build_pipeline_args(plse_instance *h, int p, uint64_t seed) {
     A.gather = GatherArgs{ctl, at<int32_t>(h, L.acc), S_all, f_all, at<uint64_t>(h, L.uid),
                           at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc), at<uint8_t>(h, L.S_tmp),
                           at<int32_t>(h, L.f_tmp), at<uint64_t>(h, L.uid_tmp),
-                          at<uint64_t>(h, L.hist_tmp), at<int32_t>(h, L.hc_tmp), p, st};
+                          at<uint64_t>(h, L.hist_tmp), at<int32_t>(h, L.hc_tmp),
+                          at<int32_t>(h, L.pos), p, st};
     A.hash = HashArgs{ctl, at<uint64_t>(h, L.uid), at<uint64_t>(h, L.hkeys),
                       at<int32_t>(h, L.hvals), p, L.hsize};
-    A.match = MatchArgs{ctl, at<int16_t>(h, L.D), at<int32_t>(h, L.acc), at<uint64_t>(h, L.uid),
-                        at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc), at<uint64_t>(h, L.hkeys),
-                        at<int32_t>(h, L.hvals), at<int32_t>(h, L.partner),
-                        at<int32_t>(h, L.dpart), p, m, L.hsize, h->P.hist_len};
+    A.match = MatchArgs{ctl, at<int16_t>(h, L.D), at<int32_t>(h, L.acc), at<int32_t>(h, L.pos),
+                        at<uint64_t>(h, L.uid), at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc),
+                        at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals),
+                        at<int32_t>(h, L.partner), at<int32_t>(h, L.dpart), p, m, m, L.hsize,
+                        h->P.hist_len};
     A.aux = AuxArgs{ctl, S_all, at<int32_t>(h, L.partner), at<int32_t>(h, L.dpart),
                     at<uint8_t>(h, L.S_off), p, h->nv, st, 0, h->P.beta_num, h->P.beta_den, slo,
                     shi};
@@ -1207,9 +1211,9 @@ int plse_stage_match(plse_handle h, int32_t p, void *stream, const int16_t *D,
     const Layout &L = h->L;
     h->args.hash = HashArgs{nullptr, uid, at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals), p,
                             L.hsize};
-    h->args.match = MatchArgs{nullptr, D, nullptr, uid, hist, hcount, at<uint64_t>(h, L.hkeys),
-                              at<int32_t>(h, L.hvals), partner, dpart, p, p, L.hsize,
-                              h->P.hist_len};
+    h->args.match = MatchArgs{nullptr, D, nullptr, nullptr, uid, hist, hcount,
+                              at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals), partner, dpart,
+                              p, p, p, L.hsize, h->P.hist_len};
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_hash(single(h, &ArgBlock::hash), 1, p, L.hsize, s));
     HIP_TRY(launch_match(single(h, &ArgBlock::match), 1, p, s));

@@ -352,6 +352,7 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     if (a.keys_in_lds)
         for (int q = tid; q < (P2 >> 2); q += nthr) select_keys(a, (uint32_t)gen, q, K);
     for (int q = tid; q < nbw; q += nthr) blocked[q] = 0u;
+    for (int q = tid; q < m; q += nthr) *gptr(a.pos + q) = -1;
     __syncthreads();
     for (int k = 2; k <= (a.keys_in_lds ? P2 : 1); k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -459,6 +460,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const ArgList L) {
         a.f_tmp[r] = a.f_all[x];
         a.uid_tmp[r] = old ? a.uid[x] : (((uint64_t)(uint32_t)a.ctl->gen << 32) | (uint32_t)(x - a.p));
         a.hc_tmp[r] = old ? a.hc[x] : 0;
+        *gptr(a.pos + x) = r;
     }
     if (old) a.hist_tmp[(size_t)r * kHist + lane] = a.hist[(size_t)x * kHist + lane];
 }
@@ -557,11 +559,15 @@ __global__ __launch_bounds__(256) void match_kernel(const ArgList L) {
         // flight per lane
         uint64_t lb = ~0ull;
         if (a.idx) {
+            // the row in D order (coalesced); pos names the individual of
+            // each entry, -1 for candidates not selected
 #pragma unroll 8
-            for (int j = lane; j < a.p; j += 64) {
-                const int aj = *gptr(a.idx + j);
-                const uint32_t d = (uint16_t)*gptr(row + aj);
-                const bool ok = j != i && (pass != 0 || !((excl[j >> 5] >> (j & 31)) & 1u));
+            for (int x = lane; x < a.m; x += 64) {
+                const int j = *gptr(a.pos + x);
+                const uint32_t d = (uint16_t)*gptr(row + x);
+                const int jc = j < 0 ? 0 : j;
+                const bool ok = j >= 0 && j != i &&
+                                (pass != 0 || !((excl[jc >> 5] >> (jc & 31)) & 1u));
                 const uint64_t key = ok ? (((uint64_t)d << 32) | (uint32_t)j) : ~0ull;
                 lb = key < lb ? key : lb;
             }

@@ -102,6 +102,7 @@ struct SelectArgs {
     uint64_t *keys_g;        // [pow2] global scratch (when not in LDS)
     int32_t *rej;            // [m] scratch
     int32_t *acc;            // [p] out
+    int32_t *pos;            // [m] out: -1 (the fill; gather sets accepted ones)
     int32_t p, m, ld, nv, pow2, keys_in_lds, gen_fixed;
     int64_t spacing;
     uint32_t seed_lo, seed_hi;
@@ -119,6 +120,7 @@ struct GatherArgs {
     int32_t *f_tmp;
     uint64_t *uid_tmp, *hist_tmp;
     int32_t *hc_tmp;
+    int32_t *pos;            // [m] new index of each accepted candidate
     int32_t p, stride;
 };
 
@@ -133,14 +135,15 @@ struct HashArgs {
 struct MatchArgs {
     const Ctl *ctl;
     const int16_t *D;        // distances, row/col through idx (identity if null)
-    const int32_t *idx;
+    const int32_t *idx;      // [p] row of D of each individual
+    const int32_t *pos;      // [m] individual of each row of D, -1 if none (with idx)
     const uint64_t *uid;
     uint64_t *hist;          // [p][kHist]
     int32_t *hc;
     const uint64_t *hkeys;
     const int32_t *hvals;
     int32_t *partner, *dpart;
-    int32_t p, ld, hsize, hist_len;
+    int32_t p, m, ld, hsize, hist_len;  // m: rows of D scanned through pos
 };
 
 struct AuxArgs {
