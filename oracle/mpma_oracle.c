@@ -62,6 +62,7 @@ uint32_t orc_tie16(uint32_t wv, uint32_t wk, uint32_t v, uint32_t k) {
 #define TAG_PLITS2     0x12u
 #define TAG_SELECT     0x21u
 #define TAG_XOVER      0x31u
+#define TAG_MATCH      0x41u
 
 /* Counter = (instance key 0, slot, gen<<8 | tag, index); key = seed halves. */
 static void draw(uint64_t seed, uint32_t slot, uint32_t gen, uint32_t tag, uint32_t idx,
@@ -549,10 +550,19 @@ void orc_select(int32_t nv, int32_t p, int64_t spacing, uint64_t seed, int32_t g
 /* neighbour (ties: lowest slot) among the individuals it has not yet been  */
 /* crossed with; if all are excluded, the plain nearest neighbour.          */
 /* ------------------------------------------------------------------------ */
-void orc_match(int32_t p, const int32_t *D, const uint64_t *uid, uint64_t *hist,
-               int32_t *hcount, int32_t hlen, int32_t *partner, int32_t *dpart) {
+void orc_match_mode(int32_t p, const int32_t *D, const uint64_t *uid, uint64_t *hist,
+                    int32_t *hcount, int32_t hlen, int32_t mode, uint64_t seed, int32_t gen,
+                    int32_t *partner, int32_t *dpart) {
     for (int i = 0; i < p; i++) {
         int best = -1;
+        if (mode == ORC_M_RANDOM) {
+            /* Section 5.3: the second parent is drawn uniformly among the
+             * other p - 1 individuals. */
+            uint32_t w[4];
+            draw(seed, (uint32_t)i, (uint32_t)gen, TAG_MATCH, 0u, w);
+            best = (int)scale(w[0], (uint32_t)(p - 1));
+            if (best >= i) best++;
+        }
         for (int pass = 0; pass < 2 && best < 0; pass++)
             for (int j = 0; j < p; j++) {
                 if (j == i) continue;
@@ -576,21 +586,30 @@ void orc_match(int32_t p, const int32_t *D, const uint64_t *uid, uint64_t *hist,
     }
 }
 
+void orc_match(int32_t p, const int32_t *D, const uint64_t *uid, uint64_t *hist,
+               int32_t *hcount, int32_t hlen, int32_t *partner, int32_t *dpart) {
+    orc_match_mode(p, D, uid, hist, hcount, hlen, ORC_M_NEAREST, 0, 0, partner, dpart);
+}
+
 /* ------------------------------------------------------------------------ */
 /* AUX crossover (Alg. 5): vertex v inherits S_i(v) with probability        */
 /* p_ij = 1 - |V| / (beta * D_ij) (Eq. 9), else S_j(v).  The probability is */
 /* the integer threshold floor((beta*D - |V|) * 2^32 / (beta*D)) on a 32-bit */
 /* draw, and 0 when beta*D <= |V|.                                          */
 /* ------------------------------------------------------------------------ */
-void orc_aux(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num,
-             int64_t beta_den, const uint8_t *S, const int32_t *partner, const int32_t *dpart,
-             uint8_t *S_off) {
+void orc_aux_mode(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num,
+                  int64_t beta_den, int32_t mode, const uint8_t *S, const int32_t *partner,
+                  const int32_t *dpart, uint8_t *S_off) {
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < p; i++) {
         int j = partner[i];
         uint64_t bd = (uint64_t)beta_num * (uint64_t)dpart[i];
         uint64_t bv = (uint64_t)beta_den * (uint64_t)nv;
         uint64_t thr = (bd <= bv) ? 0 : (((bd - bv) << 32) / bd);
+        /* UX: p_ij fixed at 1/2 (Section 3.5.2); no crossover: the offspring
+         * is a copy of its first parent (Section 5.2) */
+        if (mode == ORC_X_UX) thr = 1ull << 31;
+        if (mode == ORC_X_NONE) thr = 1ull << 32;
         for (int v = 0; v < nv; v++) {
             uint32_t w[4];
             draw(seed, (uint32_t)i, (uint32_t)gen, TAG_XOVER, (uint32_t)v >> 2, w);
@@ -598,6 +617,12 @@ void orc_aux(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num
                 ((uint64_t)w[v & 3] < thr) ? S[(size_t)i * nv + v] : S[(size_t)j * nv + v];
         }
     }
+}
+
+void orc_aux(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num,
+             int64_t beta_den, const uint8_t *S, const int32_t *partner, const int32_t *dpart,
+             uint8_t *S_off) {
+    orc_aux_mode(nv, p, seed, gen, beta_num, beta_den, ORC_X_AUX, S, partner, dpart, S_off);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -680,8 +705,10 @@ int32_t orc_run(const void *h, const int64_t *P, int32_t p, int32_t G, uint64_t 
         memcpy(hist, histn, sizeof(uint64_t) * (size_t)p * ORC_HMAX);
 
         /* parent matching and AUX offspring for the next generation */
-        orc_match(p, Dn, uid, hist, hc, hlen, partner, dpart);
-        orc_aux(nv, p, seed, g, P[ORC_P_BETA_NUM], P[ORC_P_BETA_DEN], Sall, partner, dpart, Soff);
+        orc_match_mode(p, Dn, uid, hist, hc, hlen, (int32_t)P[ORC_P_MATCHING], seed, g, partner,
+                       dpart);
+        orc_aux_mode(nv, p, seed, g, P[ORC_P_BETA_NUM], P[ORC_P_BETA_DEN],
+                     (int32_t)P[ORC_P_CROSSOVER], Sall, partner, dpart, Soff);
     }
     for (int g = gens; g < G; g++) {
         best_f_gen[g] = fstar;

@@ -22,8 +22,11 @@
  *   orc_distances  numpy broadcast definition.
  *   orc_select     literal transcription of Alg. 4 (with the documented
  *                  termination/fill fix).
- *   orc_match      numpy masked argmin.
- *   orc_aux        closed-form expected distances of Section 3.5.2.
+ *   orc_match      numpy masked argmin; random matching (Section 5.3): never
+ *                  the individual itself, uniform over the others.
+ *   orc_aux        closed-form expected distances of Section 3.5.2; UX keeps
+ *                  half the differing positions (binomial bound); no
+ *                  crossover copies the first parent exactly.
  *   orc_run        filled <= UB; planted instances complete; brute-force
  *                  optimum on tiny grids.
  */
@@ -47,10 +50,17 @@ enum {
     ORC_P_STOP_AT_UB,   /* 1: stop after the generation that reaches the bound   */
     ORC_P_HIST,         /* partner-history length (<= ORC_HMAX)                  */
     ORC_P_PARANOID,     /* 1: recompute the state from scratch after each move   */
+    ORC_P_CROSSOVER,    /* ORC_X_*: AUX (Alg. 5), UX or none (Section 5.2)       */
+    ORC_P_MATCHING,     /* ORC_M_*: nearest neighbour (3.5.1) or random (5.3)    */
     ORC_NPARAMS
 };
 
 #define ORC_HMAX 64
+
+/* Crossover variants (Section 3.5.2, Section 5.2). */
+enum { ORC_X_AUX = 0, ORC_X_UX = 1, ORC_X_NONE = 2 };
+/* Parent matching variants (Section 3.5.1, Section 5.3). */
+enum { ORC_M_NEAREST = 0, ORC_M_RANDOM = 1 };
 
 /* Counter vector indices (per individual, summed over phases). */
 enum {
@@ -107,11 +117,20 @@ void orc_select(int32_t nv, int32_t p, int64_t spacing, uint64_t seed, int32_t g
 /* Nearest-neighbour matching with partner history (Section 3.5.1). */
 void orc_match(int32_t p, const int32_t *D, const uint64_t *uid, uint64_t *hist,
                int32_t *hcount, int32_t hlen, int32_t *partner, int32_t *dpart);
+/* The same with a matching variant (ORC_M_*); random matching draws from
+ * (seed, slot i, generation gen). */
+void orc_match_mode(int32_t p, const int32_t *D, const uint64_t *uid, uint64_t *hist,
+                    int32_t *hcount, int32_t hlen, int32_t mode, uint64_t seed, int32_t gen,
+                    int32_t *partner, int32_t *dpart);
 
 /* AUX crossover (Alg. 5, Eq. 9). */
 void orc_aux(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num,
              int64_t beta_den, const uint8_t *S, const int32_t *partner,
              const int32_t *dpart, uint8_t *S_off);
+/* The same with a crossover variant (ORC_X_*). */
+void orc_aux_mode(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num,
+                  int64_t beta_den, int32_t mode, const uint8_t *S, const int32_t *partner,
+                  const int32_t *dpart, uint8_t *S_off);
 
 /* Whole MPMA run (Alg. 2).  best_f_gen[G], counters_gen[G*ORC_NCOUNTERS]
  * (zero past the last generation run).  final_S (p*|V|) may be NULL.

@@ -15,9 +15,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-NPARAMS = 10
+NPARAMS = 12
 P_DEPTH1, P_DEPTH2, P_ALPHA_NUM, P_ALPHA_DEN, P_BETA_NUM, P_BETA_DEN, P_SPACING, \
-    P_STOP_AT_UB, P_HIST, P_PARANOID = range(NPARAMS)
+    P_STOP_AT_UB, P_HIST, P_PARANOID, P_CROSSOVER, P_MATCHING = range(NPARAMS)
+X_AUX, X_UX, X_NONE = 0, 1, 2        # crossover variants (Section 3.5.2, Section 5.2)
+M_NEAREST, M_RANDOM = 0, 1           # matching variants (Section 3.5.1, Section 5.3)
 
 NCOUNTERS = 8
 COUNTER_NAMES = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs"]
@@ -64,7 +66,10 @@ def lib():
         L.orc_distances.argtypes = [i32, i32, P, i32, P, P]
         L.orc_select.argtypes = [i32, i32, ctypes.c_int64, u64, i32, P, P, P]
         L.orc_match.argtypes = [i32, P, P, P, P, i32, P, P]
+        L.orc_match_mode.argtypes = [i32, P, P, P, P, i32, i32, u64, i32, P, P]
         L.orc_aux.argtypes = [i32, i32, u64, i32, ctypes.c_int64, ctypes.c_int64, P, P, P, P]
+        L.orc_aux_mode.argtypes = [i32, i32, u64, i32, ctypes.c_int64, ctypes.c_int64, i32, P,
+                                   P, P, P]
         L.orc_run.restype = i32
         L.orc_run.argtypes = [P, P, i32, i32, u64, P, P, P, P, P, P]
         _lib = L
@@ -76,7 +81,8 @@ def _ptr(a: np.ndarray):
 
 
 def default_params(nv: int, n: int, depth: int | None = None, stop_at_ub: bool = False,
-                   paranoid: bool = False) -> np.ndarray:
+                   paranoid: bool = False, crossover: int = X_AUX,
+                   matching: int = M_NEAREST) -> np.ndarray:
     """Paper defaults (Table 1, Section 3.3) with an optional total depth.
 
     With a depth d, phase 2 keeps its 2|V| iterations and phase 1 gets the rest.
@@ -93,6 +99,8 @@ def default_params(nv: int, n: int, depth: int | None = None, stop_at_ub: bool =
     P[P_STOP_AT_UB] = int(stop_at_ub)
     P[P_HIST] = 64
     P[P_PARANOID] = int(paranoid)
+    P[P_CROSSOVER] = int(crossover)
+    P[P_MATCHING] = int(matching)
     return P
 
 
@@ -209,7 +217,8 @@ def select(nv: int, p: int, spacing: int, seed: int, gen: int, f_all, D_all) -> 
     return acc
 
 
-def match(D, uid, hist, hcount, hlen: int = 64):
+def match(D, uid, hist, hcount, hlen: int = 64, mode: int = M_NEAREST, seed: int = 0,
+          gen: int = 0):
     """Returns (partner, dpart, hist', hcount')."""
     p = D.shape[0]
     D = np.ascontiguousarray(D, dtype=np.int32)
@@ -218,17 +227,18 @@ def match(D, uid, hist, hcount, hlen: int = 64):
     hcount = np.array(hcount, dtype=np.int32, copy=True)
     partner = np.zeros(p, dtype=np.int32)
     dpart = np.zeros(p, dtype=np.int32)
-    lib().orc_match(p, _ptr(D), _ptr(uid), _ptr(hist), _ptr(hcount), hlen, _ptr(partner),
-                    _ptr(dpart))
+    lib().orc_match_mode(p, _ptr(D), _ptr(uid), _ptr(hist), _ptr(hcount), hlen, mode, seed, gen,
+                         _ptr(partner), _ptr(dpart))
     return partner, dpart, hist, hcount
 
 
-def aux(seed: int, gen: int, S, partner, dpart, beta_num: int = 20, beta_den: int = 1):
+def aux(seed: int, gen: int, S, partner, dpart, beta_num: int = 20, beta_den: int = 1,
+        mode: int = X_AUX):
     S = np.ascontiguousarray(S, dtype=np.uint8)
     p, nv = S.shape
     out = np.zeros_like(S)
     partner = np.ascontiguousarray(partner, dtype=np.int32)
     dpart = np.ascontiguousarray(dpart, dtype=np.int32)
-    lib().orc_aux(nv, p, seed, gen, beta_num, beta_den, _ptr(S), _ptr(partner), _ptr(dpart),
-                  _ptr(out))
+    lib().orc_aux_mode(nv, p, seed, gen, beta_num, beta_den, mode, _ptr(S), _ptr(partner),
+                       _ptr(dpart), _ptr(out))
     return out

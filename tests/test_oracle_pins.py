@@ -370,6 +370,65 @@ def test_aux_expected_distances(oracle_mod):
     np.testing.assert_array_equal(c2[0], S[1])
 
 
+def test_aux_variants_ux_and_no_crossover(oracle_mod):
+    """Section 5.2: without crossover the offspring is its first parent; UX
+    (p_ij = 1/2, Section 3.5.2) takes each differing position from either
+    parent with probability 1/2, whatever D_ij and beta are."""
+    rng = np.random.default_rng(1)
+    nv, K = 300, 400
+    S = rng.integers(1, 9, size=(2 * K, nv), dtype=np.uint8)
+    partner = np.concatenate([np.arange(K, 2 * K), np.arange(K)]).astype(np.int32)
+    dpart = rng.integers(1, nv, size=2 * K).astype(np.int32)
+    none = oracle_mod.aux(7, 2, S, partner, dpart, 20, 1, mode=oracle_mod.X_NONE)
+    np.testing.assert_array_equal(none, S)
+    ux = oracle_mod.aux(7, 2, S, partner, dpart, 20, 1, mode=oracle_mod.X_UX)[:K]
+    ux2 = oracle_mod.aux(7, 2, S, partner, np.full(2 * K, 5, np.int32), 3, 1,
+                         mode=oracle_mod.X_UX)[:K]
+    np.testing.assert_array_equal(ux, ux2)  # independent of D_ij and beta
+    assert np.all((ux == S[:K]) | (ux == S[K:]))
+    diff = S[:K] != S[K:]
+    took_i = (ux == S[:K]) & diff
+    n_diff = int(diff.sum())
+    frac = took_i.sum() / n_diff
+    assert abs(frac - 0.5) < 4 * np.sqrt(0.25 / n_diff)
+
+
+def test_random_matching_is_uniform_over_the_others(oracle_mod):
+    """Section 5.3: the second parent is any other individual, uniformly; it
+    does not depend on the distances, and D_ij is reported for it."""
+    p, G = 6, 3000
+    rng = np.random.default_rng(2)
+    D = rng.integers(0, 50, size=(p, p)).astype(np.int32)
+    D2 = rng.integers(0, 50, size=(p, p)).astype(np.int32)
+    uid = np.arange(p, dtype=np.uint64)
+    counts = np.zeros((p, p))
+    for g in range(1, G + 1):
+        hist = np.zeros((p, 64), dtype=np.uint64)
+        hc = np.zeros(p, dtype=np.int32)
+        partner, dpart, _, _ = oracle_mod.match(D, uid, hist, hc, mode=oracle_mod.M_RANDOM,
+                                                seed=99, gen=g)
+        if g <= 20:
+            other, _, _, _ = oracle_mod.match(D2, uid, hist, hc, mode=oracle_mod.M_RANDOM,
+                                              seed=99, gen=g)
+            np.testing.assert_array_equal(partner, other)
+            np.testing.assert_array_equal(dpart, D[np.arange(p), partner])
+        assert np.all(partner != np.arange(p))
+        counts[np.arange(p), partner] += 1
+    expect = G / (p - 1)
+    off = ~np.eye(p, dtype=bool)
+    assert np.all(np.abs(counts[off] - expect) < 5 * np.sqrt(expect))
+
+
+def test_run_variants_stay_legal(oracle_mod):
+    w = gen.workload_small()
+    I = oracle_mod.Instance(w["grid"])
+    for xo, mt in ((oracle_mod.X_UX, oracle_mod.M_NEAREST), (oracle_mod.X_NONE, oracle_mod.M_NEAREST),
+                   (oracle_mod.X_AUX, oracle_mod.M_RANDOM)):
+        r = I.run(I.params(depth=w["depth"], crossover=xo, matching=mt), 16, 3, w["seed"])
+        assert r["filled"] <= I.ub
+        assert gen.is_partial_latin(r["grid"])
+
+
 # --- whole run (Alg. 2) ---------------------------------------------------------------------
 def test_run_small_planted_reaches_optimum(oracle_mod):
     w = gen.workload_small()
