@@ -93,6 +93,12 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *   "spacing"     minimum spacing factor gamma of Section 3.4 (10)
  *   "stop_at_ub"  1: stop after the generation whose best reaches the bound
  *   "nn_history"  partner-history length, 0..64 (64)
+ *   "crossover"   0 AUX (Alg. 5, default), 1 UX (p_ij fixed at 1/2, Section
+ *                 3.5.2), 2 none: the offspring copies its first parent
+ *                 (Section 5.2)
+ *   "matching"    0 nearest neighbour with partner history (Section 3.5.1,
+ *                 default), 1 random: a uniformly drawn other individual
+ *                 (Section 5.3); plse_stage_match always matches nearest
  *   "slots_per_lane" 2, 4 or 8: candidate moves one lane evaluates per PLITS
  *                 round (default 0: chosen from the domain sizes)
  *   "waves_per_block" 1, 2 or 4: PLITS launch shape (default: chosen from the
@@ -238,26 +244,28 @@ int plse_stage_aux(plse_handle h, int32_t population, int32_t gen, uint64_t seed
  * Serving: continuous batching of solve requests on one device.
  *
  * A server owns a device arena (caller memory, hbm_budget_bytes) and a worker
- * thread.  Requests wait in arrival order; at every generation boundary the
- * worker retires finished requests and admits waiting ones while their
- * workspace (plse_workspace_bytes) fits in the free arena and fewer than
- * max_slots are resident.  Each step runs one generation of Alg. 2 for every
- * resident request in batched launches (as plse_solve_batch), so requests
- * that arrive while others run share the device with them.  Each result is
- * identical to plse_solve of the same instance, parameters, population,
- * generations and seed, whatever else is resident.
+ * thread.  Requests wait in arrival order; the worker admits them while their
+ * workspace (plse_workspace_bytes) fits in the free arena (first fit) and
+ * fewer than max_slots are resident.  Every resident request runs on a
+ * stream of its own, with up to two generations of Alg. 2 enqueued ahead, so
+ * requests that arrive while others run share the device with them and none
+ * waits for another's generations; a finished request's workspace returns
+ * to the arena.  Each result is identical to plse_solve of the same
+ * instance, parameters, population, generations and seed, whatever else is
+ * resident.
  *
  * plse_server_create: device_ptr/hbm_budget_bytes the arena (256-byte
  *   aligned, caller-owned, must outlive the server); max_slots >= 1; stream
- *   the HIP stream the worker uses.
+ *   orders the server's work after work already queued on it (the requests'
+ *   own streams wait for it once, at creation).
  * plse_server_submit: the handle is used by the server until its result has
  *   been polled (do not touch it meanwhile).  Returns PLSE_E_CAPACITY if the
  *   request's workspace can never fit the arena; *ticket identifies it.
  * plse_server_poll: PLSE_PENDING while the request runs; then fills the grid
  *   (host n*n), filled and the timing record, returns the request's own status
  *   (PLSE_OK, or the error that ended it) and forgets the ticket.
- * plse_server_destroy: stops the worker after the resident requests finish
- *   their current generation; waiting and resident requests are dropped.
+ * plse_server_destroy: stops the worker, waits for the work enqueued for
+ *   resident requests, and drops waiting and resident requests.
  */
 typedef struct plse_server_s *plse_server;
 

@@ -427,10 +427,10 @@ void build_pipeline_args(plse_instance *h, int p, uint64_t seed) {
                         at<uint64_t>(h, L.uid), at<uint64_t>(h, L.hist), at<int32_t>(h, L.hc),
                         at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals),
                         at<int32_t>(h, L.partner), at<int32_t>(h, L.dpart), p, m, m, L.hsize,
-                        h->P.hist_len};
+                        h->P.hist_len, h->P.matching, 0, slo, shi};
     A.aux = AuxArgs{ctl, S_all, at<int32_t>(h, L.partner), at<int32_t>(h, L.dpart),
-                    at<uint8_t>(h, L.S_off), p, h->nv, st, 0, h->P.beta_num, h->P.beta_den, slo,
-                    shi};
+                    at<uint8_t>(h, L.S_off), p, h->nv, st, 0, h->P.crossover, h->P.beta_num,
+                    h->P.beta_den, slo, shi};
 }
 
 // Launch `fn` over the instances `hs`, kMaxLaunch at a time.
@@ -886,6 +886,8 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
     h->P.spacing = 10;
     h->P.stop_at_ub = 0;
     h->P.hist_len = kHist;
+    h->P.crossover = 0;  // AUX
+    h->P.matching = 0;   // nearest neighbour
     *out = h;
     return PLSE_OK;
 }
@@ -950,6 +952,12 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "nn_history") {
         if (v < 0 || v > kHist) return PLSE_E_PARAM;
         P.hist_len = (int32_t)v;
+    } else if (k == "crossover") {
+        if (v < 0 || v > 2) return PLSE_E_PARAM;
+        P.crossover = (int32_t)v;
+    } else if (k == "matching") {
+        if (v < 0 || v > 1) return PLSE_E_PARAM;
+        P.matching = (int32_t)v;
     } else if (k == "slots_per_lane") {
         if (v != 0 && v != 2 && v != 4 && v != 8) return PLSE_E_PARAM;
         h->spl = (int)v;
@@ -982,6 +990,8 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "spacing") *v = P.spacing;
     else if (k == "stop_at_ub") *v = P.stop_at_ub;
     else if (k == "nn_history") *v = P.hist_len;
+    else if (k == "crossover") *v = P.crossover;
+    else if (k == "matching") *v = P.matching;
     else if (k == "slots_per_lane") *v = choose_spl(h);
     else if (k == "waves_per_block") *v = choose_wpb(h);
     else if (k == "fail_at_generation") *v = h->fail_at;
@@ -1213,7 +1223,7 @@ int plse_stage_match(plse_handle h, int32_t p, void *stream, const int16_t *D,
                             L.hsize};
     h->args.match = MatchArgs{nullptr, D, nullptr, nullptr, uid, hist, hcount,
                               at<uint64_t>(h, L.hkeys), at<int32_t>(h, L.hvals), partner, dpart,
-                              p, p, p, L.hsize, h->P.hist_len};
+                              p, p, p, L.hsize, h->P.hist_len, 0, 0, 0u, 0u};
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_hash(single(h, &ArgBlock::hash), 1, p, L.hsize, s));
     HIP_TRY(launch_match(single(h, &ArgBlock::match), 1, p, s));
@@ -1230,7 +1240,8 @@ int plse_stage_aux(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void *s
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     RC_TRY(stage_prepare(h, p, s));
     h->args.aux = AuxArgs{nullptr, S, partner, dpart, S_off, p, h->nv, h->stride, gen,
-                          h->P.beta_num, h->P.beta_den, (uint32_t)seed, (uint32_t)(seed >> 32)};
+                          h->P.crossover, h->P.beta_num, h->P.beta_den, (uint32_t)seed,
+                          (uint32_t)(seed >> 32)};
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_aux(single(h, &ArgBlock::aux), 1, p, s));
     return PLSE_OK;

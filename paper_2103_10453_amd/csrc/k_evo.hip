@@ -554,6 +554,16 @@ __global__ __launch_bounds__(256) void match_kernel(const ArgList L) {
     const int ai = a.idx ? *gptr(a.idx + i) : i;
     const int16_t *row = a.D + (size_t)ai * a.ld;
     uint64_t best = ~0ull;
+    if (a.mode == 1) {
+        // random matching (Section 5.3): uniform over the other p - 1
+        int gen = a.gen_fixed;
+        if (gen == 0) gen = a.ctl->gen;
+        const U4 w = draw(a.seed_lo, a.seed_hi, (uint32_t)i, (uint32_t)gen, TAG_MATCH, 0u);
+        int j = (int)(((uint64_t)w.x * (uint64_t)(uint32_t)(a.p - 1)) >> 32);
+        j += (j >= i) ? 1 : 0;
+        const int aj = a.idx ? *gptr(a.idx + j) : j;
+        best = ((uint64_t)(uint16_t)*gptr(row + aj) << 32) | (uint32_t)j;
+    }
     for (int pass = 0; pass < 2 && best == ~0ull; ++pass) {
         // branch-free body, unrolled: several index and distance loads in
         // flight per lane
@@ -618,7 +628,11 @@ __global__ __launch_bounds__(256) void aux_kernel(const ArgList L) {
     if (j < 0 || j >= a.p) j = i;  // out-of-range partner: no crossover
     const uint64_t bd = (uint64_t)a.beta_num * (uint64_t)(uint32_t)a.dpart[i];
     const uint64_t bv = (uint64_t)a.beta_den * (uint64_t)a.nv;
-    const uint64_t thr = (bd <= bv) ? 0ull : (((bd - bv) << 32) / bd);
+    // UX fixes p_ij at 1/2 (Section 3.5.2); without crossover the offspring
+    // copies its first parent (Section 5.2)
+    const uint64_t thr = a.mode == 1   ? (1ull << 31)
+                         : a.mode == 2 ? (1ull << 32)
+                                       : ((bd <= bv) ? 0ull : (((bd - bv) << 32) / bd));
     const uint32_t *si = reinterpret_cast<const uint32_t *>(a.S + (size_t)i * a.stride);
     const uint32_t *sj = reinterpret_cast<const uint32_t *>(a.S + (size_t)j * a.stride);
     uint32_t *so = reinterpret_cast<uint32_t *>(a.S_off + (size_t)i * a.stride);

@@ -144,6 +144,8 @@ struct MatchArgs {
     const int32_t *hvals;
     int32_t *partner, *dpart;
     int32_t p, m, ld, hsize, hist_len;  // m: rows of D scanned through pos
+    int32_t mode, gen_fixed;            // matching variant; generation (0: from ctl)
+    uint32_t seed_lo, seed_hi;
 };
 
 struct AuxArgs {
@@ -152,6 +154,7 @@ struct AuxArgs {
     const int32_t *partner, *dpart;
     uint8_t *S_off;          // [p][stride]
     int32_t p, nv, stride, gen_fixed;
+    int32_t mode;            // crossover variant: 0 AUX, 1 UX, 2 none
     int64_t beta_num, beta_den;
     uint32_t seed_lo, seed_hi;
 };

@@ -22,6 +22,7 @@ enum Tag : uint32_t {
     TAG_PLITS2 = 0x12,
     TAG_SELECT = 0x21,
     TAG_XOVER = 0x31,
+    TAG_MATCH = 0x41,
 };
 
 // Reduced graph of one instance, as device pointers into the workspace.
@@ -50,6 +51,8 @@ struct Params {
     int64_t spacing;
     int32_t stop_at_ub;
     int32_t hist_len;
+    int32_t crossover;  // 0 AUX (Alg. 5), 1 UX (p_ij = 1/2), 2 none (Section 5.2)
+    int32_t matching;   // 0 nearest neighbour (Section 3.5.1), 1 random (Section 5.3)
 };
 
 // Device control block of a solve (one per handle).

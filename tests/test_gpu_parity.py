@@ -223,7 +223,50 @@ def test_aux_parity(torch_cuda, oracle_mod, name, p, seed):
     np.testing.assert_array_equal(_np(out)[:, :I.nv], oo)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_aux_variant_parity(torch_cuda, oracle_mod, mode):
+    """UX (1) and no crossover (2), Section 3.5.2 and Section 5.2."""
+    g = _instances()["greedy20_50"]
+    _say(f"aux variant {mode}")
+    s = P.Solver(g, crossover=mode)
+    I = oracle_mod.Instance(g)
+    p, seed = 40, 8
+    rng = np.random.default_rng(seed)
+    S = np.zeros((p, s.stride), dtype=np.uint8)
+    S[:, :I.nv] = rng.integers(0, I.n + 1, size=(p, I.nv))
+    partner = np.array([(i + 1 + rng.integers(0, p - 1)) % p for i in range(p)], dtype=np.int32)
+    dpart = rng.integers(0, I.nv + 1, size=p).astype(np.int32)
+    import torch
+    out = s.stage_aux(torch.from_numpy(S).cuda(), torch.from_numpy(partner).cuda(),
+                      torch.from_numpy(dpart).cuda(), 3, seed)
+    torch.cuda.synchronize()
+    oo = oracle_mod.aux(seed, 3, S[:, :I.nv], partner, dpart, mode=mode)
+    np.testing.assert_array_equal(_np(out)[:, :I.nv], oo)
+
+
 # --- whole runs -------------------------------------------------------------------------
+@pytest.mark.parametrize("name,p,G,depth,crossover,matching", [
+    ("planted10", 32, 6, 600, 1, 0),
+    ("greedy12_60", 24, 5, 1440, 2, 0),
+    ("greedy20_50", 32, 4, 2000, 0, 1),
+    ("greedy12_60", 24, 5, 1440, 1, 1),
+])
+def test_solve_variant_parity(torch_cuda, oracle_mod, name, p, G, depth, crossover, matching):
+    """Whole runs with the crossover / matching variants of Sections 5.2-5.3."""
+    g = _instances()[name]
+    _say(f"solve variant {name} p={p} G={G} crossover={crossover} matching={matching}")
+    s = P.Solver(g, depth=depth, crossover=crossover, matching=matching)
+    seed = 777 + p
+    grid, filled = s.solve(p, G, seed)
+    st = s.stats()
+    I = oracle_mod.Instance(g)
+    r = I.run(I.params(depth=depth, crossover=crossover, matching=matching), p, G, seed)
+    assert filled == r["filled"]
+    np.testing.assert_array_equal(grid, r["grid"])
+    np.testing.assert_array_equal(st["best_f_per_gen"], r["best_f"][:r["gens"]])
+    np.testing.assert_array_equal(st["counters_per_gen"], r["counters"][:r["gens"]])
+
+
 @pytest.mark.parametrize("name,p,G,depth,stop", [
     ("planted10", 64, 20, 1000, 0),
     ("greedy12_60", 32, 6, 1440, 0),
