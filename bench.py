@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n50", choices=["n50", "n70_30", "n70_50", "n70_70",
-                                                         "small", "batch", "served"])
+                                                         "small", "batch", "served", "lsc"])
     ap.add_argument("--instances", type=int, default=256, help="batch: number of instances")
     ap.add_argument("--requests", type=int, default=16, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
@@ -171,8 +171,8 @@ def main():
         print(json.dumps({"copy_reference_bytes_read": n * 4, "copy_reference_bytes_written": n * 4}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
-              "(see DESIGN.md for how the population would shard)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; across GPUs the population would shard by "
+              "individual with one all-gather of the offspring per generation", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -185,6 +185,8 @@ def main():
         return bench_batch(args, gen, plse)
     if args.workload == "served":
         return bench_served(args, gen, plse)
+    if args.workload == "lsc":
+        return bench_lsc(args, gen, plse)
     if args.workload == "n50":
         w = gen.workload_n50()
         desc = "planted n=50, 50% prefilled, population 16384, depth 10n^2 per generation"
@@ -305,6 +307,41 @@ def bench_batch(args, gen, plse):
         "one_instance_per_launch": {"value": moves_s / t_seq, "seconds": t_seq},
         "batched_seconds": t_batch, "speedup": t_seq / t_batch, "identical_results": same,
         "filled_total": int(sum(r[1] for r in res_b))}), flush=True)
+
+
+def bench_lsc(args, gen, plse):
+    """Latin square completion mode: planted instances (completable by
+    construction) solved with the stop at the bound, i.e. at f = 0; reports
+    success, generations and time to a complete square."""
+    import numpy as np
+    import torch
+    torch.cuda.set_device(0)
+    p = args.population or 4096
+    G = args.generations or 50
+    cases = [(50, 0.5), (60, 0.5), (70, 0.5), (60, 0.4)]
+    rows, moves, t_all = [], 0, 0.0
+    for k, (n, r) in enumerate(cases):
+        g = gen.planted(n, r, 7000 + k)
+        s = plse.Solver(g, depth=10 * n * n, stop_at_ub=1)
+        s.solve(p, 1, 1)  # warm-up: workspace and code
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        grid, filled = s.solve(p, G, 9000 + k)
+        t = time.perf_counter() - t0
+        st = s.stats()
+        ok = filled == n * n and gen.is_partial_latin(grid)
+        moves += int(st["totals"][1])
+        t_all += t
+        rows.append({"n": n, "prefill": r, "solved": bool(ok),
+                     "generations": int(st["generations_run"]), "seconds": t})
+    print(json.dumps({
+        "metric": f"LSC: planted instances completed (pop {p}, at most {G} generations)",
+        "value": sum(r["solved"] for r in rows) / len(rows), "unit": "fraction solved",
+        "n_gpus": 1, "steps": G, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "lsc: planted (n, prefill) in " + str(cases)
+                               + ", depth 10n^2, stop at f = 0", "population": p},
+        "moves_per_s": moves / t_all if t_all else None, "cases": rows}), flush=True)
 
 
 def bench_served(args, gen, plse):
