@@ -60,6 +60,7 @@ uint32_t orc_tie16(uint32_t wv, uint32_t wk, uint32_t v, uint32_t k) {
 #define TAG_INIT_PICK  0x02u
 #define TAG_PLITS1     0x11u
 #define TAG_PLITS2     0x12u
+#define TAG_PARTIAL    0x13u
 #define TAG_SELECT     0x21u
 #define TAG_XOVER      0x31u
 #define TAG_MATCH      0x41u
@@ -440,6 +441,91 @@ static void repair(const inst_t *I, uint8_t *S, int *conf, uint64_t *cnt) {
     }
 }
 
+/* PartialCol (Section 3.7, the legal-colouring tabu search of Partial-MPMA,
+ * adapted to list colouring).  S is a legal partial colouring and stays one;
+ * the search minimises f = |V_0|.  A move gives an uncoloured vertex v a
+ * colour k of D*(v) and uncolours the neighbours of v that hold k (Delta f =
+ * their number - 1); those neighbours may not take k again for T iterations
+ * unless that reaches a better f than the search's best (aspiration).  Best
+ * move, ties, tenure T = L + alpha |V_0| (after the move) and the snapshot of
+ * the best solution follow the conventions of the two-phase search.  S is
+ * updated in place to the best solution found. */
+static void partialcol(const inst_t *I, const int64_t *P, uint64_t seed, uint32_t slot,
+                       uint32_t gen, int64_t iters, uint8_t *S, work_t *W, uint64_t *cnt) {
+    int n = I->n, nv = I->nv;
+    int64_t f, c;
+    full_state(I, S, W->conf, &f, &c);
+    die_if(c != 0);
+    int64_t fbest = f;
+    memcpy(W->best, S, (size_t)nv);
+    for (size_t q = 0; q < (size_t)nv * (n + 1); q++) W->tabu[q] = 0;
+    int *gone = (int *)malloc(sizeof(int) * (size_t)(2 * n + 2));
+
+    for (int64_t it = 0; it < iters; it++) {
+        if (f == 0) break; /* complete: nothing left to colour */
+        cnt[ORC_C_ITERS]++;
+        cnt[ORC_C_ELIG] += (uint64_t)f;
+        uint32_t w[4];
+        draw(seed, slot, gen, TAG_PARTIAL, (uint32_t)it, w);
+        uint64_t best_key = UINT64_MAX;
+        int bv = -1, bk = -1;
+        int64_t bdelta = 0;
+        for (int v = 0; v < nv; v++) {
+            if (S[v] != 0) continue;
+            for (int q = I->dom_off[v]; q < I->dom_off[v + 1]; q++) {
+                int k = I->dom[q];
+                cnt[ORC_C_CANDS]++;
+                int64_t delta = (int64_t)W->conf[(size_t)v * (n + 1) + k] - 1;
+                int adm = (it >= W->tabu[(size_t)v * (n + 1) + k]) || (f + delta < fbest);
+                if (!adm) continue;
+                uint32_t t = orc_tie16(w[1], w[2], (uint32_t)v, (uint32_t)k);
+                uint64_t key = ((uint64_t)(uint32_t)(delta + 0x80000000LL) << 32) | t;
+                if (key < best_key) { best_key = key; bv = v; bk = k; bdelta = delta; }
+            }
+        }
+        if (bv < 0) {
+            cnt[ORC_C_IDLE]++;
+            continue;
+        }
+        /* bv joins class bk; its neighbours in class bk leave it */
+        int ng = 0;
+        FOR_NEIGHBOURS(I, bv, u, {
+            if (S[u] == bk) gone[ng++] = u;
+            W->conf[(size_t)u * (n + 1) + bk]++;
+        });
+        S[bv] = (uint8_t)bk;
+        for (int q = 0; q < ng; q++) {
+            int u = gone[q];
+            S[u] = 0;
+            FOR_NEIGHBOURS(I, u, x, { W->conf[(size_t)x * (n + 1) + bk]--; });
+        }
+        die_if(ng - 1 != bdelta);
+        f += bdelta;
+        cnt[ORC_C_NUPD] += 2u + 2u * (uint64_t)ng;
+        if (P[ORC_P_PARANOID]) {
+            int64_t f2, c2;
+            int *conf2 = (int *)malloc(sizeof(int) * (size_t)nv * (n + 1));
+            full_state(I, S, conf2, &f2, &c2);
+            die_if(f2 != f || c2 != 0);
+            for (int v = 0; v < nv; v++)
+                for (int q = I->dom_off[v]; q < I->dom_off[v + 1]; q++)
+                    die_if(conf2[(size_t)v * (n + 1) + I->dom[q]] !=
+                           W->conf[(size_t)v * (n + 1) + I->dom[q]]);
+            free(conf2);
+        }
+        int64_t T = (int64_t)scale(w[0], 10u) + (P[ORC_P_ALPHA_NUM] * f) / P[ORC_P_ALPHA_DEN];
+        for (int q = 0; q < ng; q++) W->tabu[(size_t)gone[q] * (n + 1) + bk] = it + 1 + T;
+        cnt[ORC_C_MOVES]++;
+        if (f < fbest) {
+            fbest = f;
+            memcpy(W->best, S, (size_t)nv);
+            cnt[ORC_C_SNAPS]++;
+        }
+    }
+    free(gone);
+    memcpy(S, W->best, (size_t)nv);
+}
+
 static void phase_lengths(const int64_t *P, int64_t *i1, int64_t *i2) {
     *i1 = P[ORC_P_DEPTH1];
     *i2 = P[ORC_P_DEPTH2];
@@ -457,11 +543,18 @@ static void plits_one(const inst_t *I, const int64_t *P, uint64_t seed, uint32_t
     phase_lengths(P, &i1, &i2);
     memcpy(S_out, S_in, (size_t)nv);
     for (int q = 0; q < ORC_NCOUNTERS; q++) cnt[q] = 0;
-    /* Phase 1 explores with phi = 1/2; phase 2 starts from phase 1's best and
-     * drives conflicts out with phi = |V| (Section 3.3). */
-    plits_phase(I, P, seed, slot, gen, 1, i1, S_out, &W, cnt, trace, trace_rows, trace_max);
-    plits_phase(I, P, seed, slot, gen, 2, i2, S_out, &W, cnt, trace, trace_rows, trace_max);
-    repair(I, S_out, W.conf, cnt);
+    if (P[ORC_P_VARIANT] == ORC_V_PARTIAL) {
+        /* Partial-MPMA (Section 3.7): the offspring is repaired into a legal
+         * partial colouring, then improved by PartialCol for the whole depth */
+        repair(I, S_out, W.conf, cnt);
+        partialcol(I, P, seed, slot, gen, i1 + i2, S_out, &W, cnt);
+    } else {
+        /* Phase 1 explores with phi = 1/2; phase 2 starts from phase 1's best
+         * and drives conflicts out with phi = |V| (Section 3.3). */
+        plits_phase(I, P, seed, slot, gen, 1, i1, S_out, &W, cnt, trace, trace_rows, trace_max);
+        plits_phase(I, P, seed, slot, gen, 2, i2, S_out, &W, cnt, trace, trace_rows, trace_max);
+        repair(I, S_out, W.conf, cnt);
+    }
     *f_out = count_uncoloured(S_out, nv);
     free(W.conf); free(W.tabu); free(W.best);
 }

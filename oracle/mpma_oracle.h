@@ -18,7 +18,9 @@
  *   orc_init       invariants: legal, maximal, prefilled kept.
  *   orc_plits      from-scratch recomputation after every move (paranoid
  *                  mode) and an independent brute-force re-derivation of every
- *                  move on tiny instances.
+ *                  move on tiny instances.  Partial-MPMA's PartialCol: the
+ *                  same recomputation check, legality after every search,
+ *                  and f never above the repaired offspring's.
  *   orc_distances  numpy broadcast definition.
  *   orc_select     literal transcription of Alg. 4 (with the documented
  *                  termination/fill fix).
@@ -52,6 +54,7 @@ enum {
     ORC_P_PARANOID,     /* 1: recompute the state from scratch after each move   */
     ORC_P_CROSSOVER,    /* ORC_X_*: AUX (Alg. 5), UX or none (Section 5.2)       */
     ORC_P_MATCHING,     /* ORC_M_*: nearest neighbour (3.5.1) or random (5.3)    */
+    ORC_P_VARIANT,      /* ORC_V_*: MPMA or Partial-MPMA (Section 3.7)           */
     ORC_NPARAMS
 };
 
@@ -61,6 +64,9 @@ enum {
 enum { ORC_X_AUX = 0, ORC_X_UX = 1, ORC_X_NONE = 2 };
 /* Parent matching variants (Section 3.5.1, Section 5.3). */
 enum { ORC_M_NEAREST = 0, ORC_M_RANDOM = 1 };
+/* Algorithm variants: MPMA, or Partial-MPMA (Section 3.7: repaired offspring
+ * and the PartialCol tabu search over legal partial colourings). */
+enum { ORC_V_MPMA = 0, ORC_V_PARTIAL = 1 };
 
 /* Counter vector indices (per individual, summed over phases). */
 enum {

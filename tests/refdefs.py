@@ -177,6 +177,70 @@ def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
     return rows, S
 
 
+def repair_greedy(S, verts):
+    """Section 3.7: uncolour the most conflicting vertex first (lowest id on
+    ties) until no conflict is left."""
+    S = list(S)
+    nv = len(verts)
+    while True:
+        cnts = [sum(1 for u in range(nv) if S[v] and S[u] == S[v] and adjacent(verts[u], verts[v]))
+                for v in range(nv)]
+        m = max(cnts) if cnts else 0
+        if m == 0:
+            return S
+        S[cnts.index(m)] = 0
+
+
+# --- PartialCol re-derived by brute force (Section 3.7) ----------------------------
+def partialcol_bruteforce(grid, S_in, seed, slot, gen, depth):
+    """Partial-MPMA's search on one offspring: greedy repair, then tabu search
+    over legal partial colourings minimising the uncoloured count.  A move
+    colours an uncoloured vertex v with k in D*(v) and uncolours v's neighbours
+    coloured k, which may not take k back for T = L + 6 f / 10 iterations
+    (f after the move) unless that beats the best f.  Every move's value is
+    recomputed from scratch.  Returns the best colouring found."""
+    verts, dom, _ = reduced_graph(grid)
+    n = len(grid)
+    nv = len(verts)
+    S = repair_greedy(S_in, verts)
+    fbest = f_of(S)
+    Sbest = list(S)
+    tabu = {}
+    for it in range(depth):
+        U = [v for v in range(nv) if S[v] == 0]
+        if not U:
+            break
+        w = draw(seed, slot, gen, 0x13, it)
+        fc = f_of(S)
+        best = None
+        for v in U:
+            for k in dom[v]:
+                S2 = list(S)
+                S2[v] = k
+                for u in range(nv):
+                    if S2[u] == k and adjacent(verts[u], verts[v]):
+                        S2[u] = 0
+                delta = f_of(S2) - fc
+                if not (it >= tabu.get((v, k), 0) or fc + delta < fbest):
+                    continue
+                key = (delta, tie16(w[1], w[2], v, k), v * (n + 1) + k)
+                if best is None or key < best[0]:
+                    best = (key, v, k, S2)
+        if best is None:
+            continue
+        _, v, k, S2 = best
+        gone = [u for u in range(nv) if S[u] == k and adjacent(verts[u], verts[v])]
+        S = S2
+        assert c_of(S, verts) == 0
+        T = ((w[0] * 10) >> 32) + (6 * f_of(S)) // 10
+        for u in gone:
+            tabu[(u, k)] = it + 1 + T
+        if f_of(S) < fbest:
+            fbest = f_of(S)
+            Sbest = list(S)
+    return Sbest
+
+
 # --- Population update, Alg. 4, transcribed literally ------------------------------
 def alg4_literal(f_all, D_all, nv, p, gamma, seed, gen):
     """Alg. 4 with its two fixes: a candidate leaves P^all once examined, and a

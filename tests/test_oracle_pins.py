@@ -254,6 +254,43 @@ def test_plits_incremental_state_equals_recomputation(oracle_mod, n, r, planted,
     assert c["cands"] >= c["iters"] and c["elig"] >= c["iters"]
 
 
+@pytest.mark.parametrize("n,r,gseed", TRACE_CASES)
+def test_partialcol_matches_bruteforce(oracle_mod, n, r, gseed):
+    """Partial-MPMA (Section 3.7): repair, then PartialCol; the oracle's result
+    equals the brute-force re-derivation that recomputes every move's value
+    from the definition."""
+    g = gen.random_greedy(n, r, gseed)
+    I = oracle_mod.Instance(g)
+    rng = np.random.default_rng(gseed)
+    verts, dom, _ = R.reduced_graph(g.tolist())
+    S0 = np.array([rng.choice([0] + d) for d in dom], dtype=np.uint8)
+    depth = 40 + 3 * I.nv
+    P = I.params(depth=depth, variant=oracle_mod.V_PARTIAL)
+    seed64 = (1 << 34) + 31 * gseed
+    S_out, f_out, cnt = I.plits(P, seed64, 2, [3], S0)
+    ref = R.partialcol_bruteforce(g.tolist(), list(S0), seed64, 3, 2, depth)
+    assert list(S_out[0]) == ref
+    assert f_out[0] == R.f_of(ref) and R.c_of(ref, verts) == 0
+    assert int(cnt[0, 7]) == R.f_of(R.repair_greedy(list(S0), verts)) - R.f_of(list(S0))
+
+
+@pytest.mark.parametrize("n,r,seed", [(12, 0.6, 2), (20, 0.7, 4), (15, 0.8, 5)])
+def test_partialcol_incremental_state_and_progress(oracle_mod, n, r, seed):
+    """Paranoid recomputation after every PartialCol move; outputs legal and
+    never worse than the repaired offspring."""
+    g = gen.random_greedy(n, r, seed)
+    I = oracle_mod.Instance(g)
+    verts, dom, _ = R.reduced_graph(g.tolist())
+    rng = np.random.default_rng(seed)
+    S0 = np.array([[rng.choice([0] + d) for d in dom] for _ in range(4)], dtype=np.uint8)
+    P = I.params(depth=10 * n * n, paranoid=True, variant=oracle_mod.V_PARTIAL)
+    S_out, f, cnt = I.plits(P, 13, 1, list(range(4)), S0)
+    for i in range(4):
+        assert R.c_of(list(S_out[i]), verts) == 0
+        assert f[i] == R.f_of(list(S_out[i]))
+        assert f[i] <= R.f_of(R.repair_greedy(list(S0[i]), verts))
+
+
 def test_plits_improves_or_keeps_start(oracle_mod):
     """Phase 2 starts from phase 1's best, and a legal start is never made worse:
     with phi = |V| a legal S with f uncoloured has F = f, and F* only decreases."""
@@ -422,9 +459,12 @@ def test_random_matching_is_uniform_over_the_others(oracle_mod):
 def test_run_variants_stay_legal(oracle_mod):
     w = gen.workload_small()
     I = oracle_mod.Instance(w["grid"])
-    for xo, mt in ((oracle_mod.X_UX, oracle_mod.M_NEAREST), (oracle_mod.X_NONE, oracle_mod.M_NEAREST),
-                   (oracle_mod.X_AUX, oracle_mod.M_RANDOM)):
-        r = I.run(I.params(depth=w["depth"], crossover=xo, matching=mt), 16, 3, w["seed"])
+    for xo, mt, va in ((oracle_mod.X_UX, oracle_mod.M_NEAREST, 0),
+                       (oracle_mod.X_NONE, oracle_mod.M_NEAREST, 0),
+                       (oracle_mod.X_AUX, oracle_mod.M_RANDOM, 0),
+                       (oracle_mod.X_AUX, oracle_mod.M_NEAREST, oracle_mod.V_PARTIAL)):
+        r = I.run(I.params(depth=w["depth"], crossover=xo, matching=mt, variant=va), 16, 3,
+                  w["seed"])
         assert r["filled"] <= I.ub
         assert gen.is_partial_latin(r["grid"])
 
