@@ -205,13 +205,14 @@ PlitsLds plits_lds(const plse_instance *h) {
 // Waves per block: the most resident waves per CU for every chunk size in
 // use; among equals the fewest waves per block, since a block keeps its LDS
 // until its slowest wave ends and searches end at very different times.
-int auto_wpb(int per_wave, const std::vector<int> &spls) {
+int auto_wpb(int per_wave, const std::vector<int> &spls, bool partial) {
     const int lim = max_lds_per_block();
     int best = 1, best_waves = -1;
     for (int w : {1, 2, 4}) {
         if (w * per_wave > lim) continue;
         int waves = 1 << 30;
-        for (int spl : spls) waves = std::min(waves, plits_waves_per_cu(spl, w, per_wave));
+        for (int spl : spls)
+            waves = std::min(waves, plits_waves_per_cu(spl, w, per_wave, partial));
         if (waves > best_waves) {
             best = w;
             best_waves = waves;
@@ -221,7 +222,8 @@ int auto_wpb(int per_wave, const std::vector<int> &spls) {
 }
 
 int choose_wpb(const plse_instance *h) {
-    return h->wpb ? h->wpb : auto_wpb(plits_lds(h).per_wave, {choose_spl(h)});
+    return h->wpb ? h->wpb
+                  : auto_wpb(plits_lds(h).per_wave, {choose_spl(h)}, h->P.variant != 0);
 }
 
 Layout plan(const plse_instance *h, int p) {
@@ -464,6 +466,7 @@ int launch_ctl(const std::vector<plse_instance *> &hs, bool reset, hipStream_t s
 // instance never runs at the occupancy of a large one.
 struct PlitsGroup {
     int spl = 8, occ = 0, lds = 0, wpb = 1;
+    bool partial = false;
     std::vector<plse_instance *> hs;
 };
 
@@ -492,7 +495,7 @@ struct Session {
 
 int launch_group(const Session &S, const PlitsGroup &g, hipStream_t s) {
     return launch_over(g.hs, &ArgBlock::plits, [&](const ArgList &L, int c) {
-        return launch_plits(L, c, S.p, g.lds, g.spl, g.wpb, s);
+        return launch_plits(L, c, S.p, g.lds, g.spl, g.wpb, g.partial, s);
     });
 }
 
@@ -632,14 +635,17 @@ void shape_session(Session &S) {
     S.groups.clear();
     for (plse_instance *h : S.hs) {
         const int spl = choose_spl(h), per = plits_lds(h).per_wave;
-        const int occ = plits_waves_per_cu(spl, 1, per);
-        auto it = std::find_if(S.groups.begin(), S.groups.end(),
-                               [&](const PlitsGroup &g) { return g.spl == spl && g.occ == occ; });
+        const bool partial = h->P.variant != 0;
+        const int occ = plits_waves_per_cu(spl, 1, per, partial);
+        auto it = std::find_if(S.groups.begin(), S.groups.end(), [&](const PlitsGroup &g) {
+            return g.spl == spl && g.occ == occ && g.partial == partial;
+        });
         if (it == S.groups.end()) {
             S.groups.push_back(PlitsGroup{});
             it = S.groups.end() - 1;
             it->spl = spl;
             it->occ = occ;
+            it->partial = partial;
         }
         it->lds = std::max(it->lds, per);
         it->hs.push_back(h);
@@ -647,7 +653,7 @@ void shape_session(Session &S) {
     for (PlitsGroup &g : S.groups) {
         bool same_wpb = true;
         for (plse_instance *h : g.hs) same_wpb = same_wpb && h->wpb == g.hs[0]->wpb;
-        g.wpb = (same_wpb && g.hs[0]->wpb) ? g.hs[0]->wpb : auto_wpb(g.lds, {g.spl});
+        g.wpb = (same_wpb && g.hs[0]->wpb) ? g.hs[0]->wpb : auto_wpb(g.lds, {g.spl}, g.partial);
         if (g.wpb * g.lds > max_lds_per_block()) g.wpb = 1;
     }
 }
@@ -888,6 +894,7 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
     h->P.hist_len = kHist;
     h->P.crossover = 0;  // AUX
     h->P.matching = 0;   // nearest neighbour
+    h->P.variant = 0;    // MPMA
     *out = h;
     return PLSE_OK;
 }
@@ -958,6 +965,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "matching") {
         if (v < 0 || v > 1) return PLSE_E_PARAM;
         P.matching = (int32_t)v;
+    } else if (k == "variant") {
+        if (v < 0 || v > 1) return PLSE_E_PARAM;
+        P.variant = (int32_t)v;
     } else if (k == "slots_per_lane") {
         if (v != 0 && v != 2 && v != 4 && v != 8) return PLSE_E_PARAM;
         h->spl = (int)v;
@@ -992,6 +1002,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "nn_history") *v = P.hist_len;
     else if (k == "crossover") *v = P.crossover;
     else if (k == "matching") *v = P.matching;
+    else if (k == "variant") *v = P.variant;
     else if (k == "slots_per_lane") *v = choose_spl(h);
     else if (k == "waves_per_block") *v = choose_wpb(h);
     else if (k == "fail_at_generation") *v = h->fail_at;
@@ -1173,7 +1184,7 @@ int plse_stage_plits(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void 
     const int wpb = choose_wpb(h);
     if (wpb * plits_lds(h).per_wave > max_lds_per_block()) return PLSE_E_ARG;
     HIP_TRY(launch_plits(single(h, &ArgBlock::plits), 1, p, plits_lds(h).per_wave,
-                         choose_spl(h), wpb, s));
+                         choose_spl(h), wpb, h->P.variant != 0, s));
     return PLSE_OK;
 }
 

@@ -199,24 +199,30 @@ struct Chunk<8> {
     }
 };
 
-template <int CH>
-__device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t slot,
+// PH 1, 2: the two phases of Section 3.3.  PH 3: PartialCol (Section 3.7),
+// the search of Partial-MPMA over legal partial colourings: the eligible
+// vertices are the uncoloured ones (a legal colouring has no conflicts), a
+// move colours one of them and uncolours its neighbours holding the colour,
+// which then may not take it back for T iterations.
+template <int CH, int PH>
+__device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
                           uint32_t gen, const uint8_t *src, uint8_t *out, uint32_t *tabu,
                           const WaveState &ws, Scal &sc, Cnt &ucnt, uint32_t &lane_cands) {
     const DevInstance &I = a.I;
     const int lane = lane_id();
     const int n = I.n, nv = I.nv, np1 = n + 1, TS = I.ts;
-    // F = phi_den f + phi_num c: phase 1 phi = 1/2, phase 2 phi = |V|.
-    const int32_t phi_num = (phase == 1) ? 1 : nv;
-    const int32_t phi_den = (phase == 1) ? 2 : 1;
-    const uint32_t tag = (phase == 1) ? TAG_PLITS1 : TAG_PLITS2;
+    // F = phi_den f + phi_num c: phase 1 phi = 1/2, phase 2 phi = |V|;
+    // PartialCol: F = f (c stays 0)
+    const int32_t phi_num = (PH == 1 || PH == 3) ? 1 : nv;
+    const int32_t phi_den = (PH == 1) ? 2 : 1;
+    const uint32_t tag = PH == 1 ? TAG_PLITS1 : (PH == 2 ? TAG_PLITS2 : TAG_PARTIAL);
     // Move values on a 16-bit scale e ordered like delta: e = delta when the
     // phase's values fit (phase 1, and phase 2 with |V| <= 64); otherwise
     // e = 4 dc + df, which orders moves as |V| dc + df does since |df| <= 1
     // and |V| >= 3.  Keys carry e + 2^15.
-    const bool squeeze = (phase == 2 && nv > 64);
-    const int32_t eA = (phase == 1) ? 1 : (squeeze ? 4 : nv);  // per unit of dc
-    const int32_t eB = (phase == 1) ? 2 : 1;                    // per unit of df
+    const bool squeeze = (PH == 2 && nv > 64);
+    const int32_t eA = (PH != 2) ? 1 : (squeeze ? 4 : nv);  // per unit of dc
+    const int32_t eB = (PH == 1) ? 2 : 1;                   // per unit of df
     const uint32_t alpha_n = (uint32_t)a.P.alpha_num, alpha_d = (uint32_t)a.P.alpha_den;
     const uint32_t m_alpha = 0xFFFFFFFFu / alpha_d;
     uint8_t *rowH = ws.H;
@@ -451,71 +457,123 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
         const int32_t hk_r = rH[k], hk_c = cH[k], ho_r = rH[old], ho_c = cH[old];
         const uint32_t *nb = I.nbr + (size_t)v * I.nl;
         const uint32_t ent0 = lane < deg ? gptr(nb)[lane] : 0u;
-        const u32x4 dmask = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
+        u32x4 dmask{0u, 0u, 0u, 0u};
+        if constexpr (PH != 3) dmask = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * v);
         const int32_t cvk = k ? hk_r + hk_c : 0;
         const int32_t cvo = old ? ho_r + ho_c - 2 : 0;
         const bool vC = (k != 0) && (cvk > 0);
         PLSE_WAVE_SYNC();
-        // 4. apply.  Counts: lanes 0-1 the leaving colour's row and column
-        //    count (-1), lanes 2-3 the entering colour's (+1), as LDS adds on
-        //    the bytes of u32 words (exact: counts stay within 0..n, nothing
-        //    carries), an add of 0 for colour 0.  Lane 0: v's colour, and v's
-        //    eligibility bit cleared (an exact add: v was eligible) unless v
-        //    stays in V_0 u C.  Lane roles are bit masks, not branches.
-        if (lane < 4) {
-            const uint32_t col = (ln_new & (uint32_t)k) | (~ln_new & (uint32_t)old);
-            const uint32_t hb = ((ln_odd & (uint32_t)(cH - ws.H)) |
-                                 (~ln_odd & (uint32_t)(rH - ws.H))) + col;
-            const uint32_t add = col != 0u ? ((ln_new & 2u) - 1u) << ((hb & 3u) * 8u) : 0u;
-            atomicAdd(reinterpret_cast<uint32_t *>(ws.H) + (hb >> 2), add);
-        }
-        if (lane == 0) {
-            ws.S[v] = (uint8_t)k;
-            atomicAdd(&ws.bm[v >> 5], (k == 0 || vC) ? 0u : 0u - (1u << (v & 31)));
-        }
-        PLSE_WAVE_SYNC();
-        // eligibility of the row/column vertices holding the old or new colour:
-        // all reads unconditional, one toggle where it changes
-        int32_t dC = 0;
-        for (int t0 = 0; t0 < deg; t0 += 64) {
-            const int t = t0 + lane;
-            const uint32_t ent = t0 == 0 ? ent0 : (t < deg ? gptr(nb)[t] : 0u);
-            const bool inrow = (ent >> 31) == 0;
-            const int u = (int)(ent & 0xFFFFu), other = (int)((ent >> 16) & 0x7FFFu);
-            const int su = ws.S[u];
-            const uint32_t bw = ws.bm[u >> 5];
-            const int rrow = inrow ? r : other, rcol = inrow ? other : c;
-            const int cu = (int)rowH[rrow * np1 + su] + (int)colH[rcol * np1 + su] - 2;
-            const bool hit = t < deg && su != 0 && (su == old || su == k);
-            const bool was = (bw >> (u & 31)) & 1u;
-            const bool now = cu > 0;
-            const bool flip = hit && (now != was);
-            if (flip) atomicXor(&ws.bm[u >> 5], 1u << (u & 31));
-            dC += (int32_t)__popcll(ballot(flip && now)) - (int32_t)__popcll(ballot(flip && !now));
-        }
-        const int32_t df = (k == 0 ? 1 : 0) - (old == 0 ? 1 : 0);
-        sc.nC += dC + (vC ? 1 : 0) - (old ? 1 : 0);
-        sc.f += df;
-        sc.c += cvk - cvo;
-        sc.F += (int64_t)phi_den * df + (int64_t)phi_num * (cvk - cvo);
-        ucnt.nupd += 2u * (old != 0) + 2u * (k != 0);
-        // tenure T = L + alpha (|V_0| + |C|) after the move; moving v back to
-        // `old` is tabu for T iterations
-        const uint32_t mp = (uint32_t)(sc.f + sc.nC);
-        const uint32_t T = scale32(w0, 10u) + udiv_by(alpha_n * mp, alpha_d, m_alpha);
-        const uint32_t until = itu + 1u + T;
-        pend_tv = (uint32_t)v;
-        pend_tu = until;
-        {
-            // the entry of the last domain colour is repeated over the rest
-            // of its chunk, where the candidate row repeats that colour
-            const uint32_t po = position_in(dmask, old);
-            const uint32_t dv = (uint32_t)(__popcll(((uint64_t)dmask.y << 32) | dmask.x) +
-                                           __popcll(((uint64_t)dmask.w << 32) | dmask.z));
-            const uint32_t nrep = po == dv ? (uint32_t)CH - dv % (uint32_t)CH : 1u;
-            pend_off = (uint32_t)lane < nrep ? (uint32_t)v * (uint32_t)TS + po + (uint32_t)lane
-                                             : 0xFFFFFFFFu;
-            pend_val = until;
+        if constexpr (PH == 3) {
+            // PartialCol: v (uncoloured) takes k; its cvk neighbours holding k
+            // (at most one per row and column) are uncoloured and may not take
+            // k back before `until`
+            if (lane < 4) {
+                const uint32_t col = (ln_new & (uint32_t)k) | (~ln_new & (uint32_t)old);
+                const uint32_t hb = ((ln_odd & (uint32_t)(cH - ws.H)) |
+                                     (~ln_odd & (uint32_t)(rH - ws.H))) + col;
+                const uint32_t add = col != 0u ? ((ln_new & 2u) - 1u) << ((hb & 3u) * 8u) : 0u;
+                atomicAdd(reinterpret_cast<uint32_t *>(ws.H) + (hb >> 2), add);
+            }
+            if (lane == 0) {
+                ws.S[v] = (uint8_t)k;
+                atomicAdd(&ws.bm[v >> 5], 0u - (1u << (v & 31)));
+            }
+            sc.f += cvk - 1;
+            sc.F = sc.f;
+            ucnt.nupd += 2u + 2u * (uint32_t)cvk;
+            const uint32_t mp = (uint32_t)sc.f;
+            const uint32_t T = scale32(w0, 10u) + udiv_by(alpha_n * mp, alpha_d, m_alpha);
+            const uint32_t until = itu + 1u + T;
+            PLSE_WAVE_SYNC();
+            for (int t0 = 0; t0 < deg; t0 += 64) {
+                const int t = t0 + lane;
+                const uint32_t ent = t0 == 0 ? ent0 : (t < deg ? gptr(nb)[t] : 0u);
+                const int u = (int)(ent & 0xFFFFu), other = (int)((ent >> 16) & 0x7FFFu);
+                if (t < deg && ws.S[u] == k) {
+                    const bool inrow = (ent >> 31) == 0;
+                    const int ur = inrow ? r : other, uc = inrow ? other : c;
+                    const int rb = ur * np1 + k, cb = n * np1 + uc * np1 + k;
+                    uint32_t *H32 = reinterpret_cast<uint32_t *>(ws.H);
+                    ws.S[u] = 0;
+                    atomicAdd(H32 + (rb >> 2), 0u - (1u << ((rb & 3) * 8)));
+                    atomicAdd(H32 + (cb >> 2), 0u - (1u << ((cb & 3) * 8)));
+                    atomicOr(&ws.bm[u >> 5], 1u << (u & 31));
+                    // tabu entry (u, k), repeated over the rest of the chunk
+                    // when k is u's last domain colour
+                    const u32x4 dm = gload4(reinterpret_cast<const u32x4 *>(I.vrec) + 2 * u);
+                    const uint32_t po = position_in(dm, k);
+                    const uint32_t du = (uint32_t)(__popcll(((uint64_t)dm.y << 32) | dm.x) +
+                                                   __popcll(((uint64_t)dm.w << 32) | dm.z));
+                    const uint32_t nrep = po == du ? (uint32_t)CH - du % (uint32_t)CH : 1u;
+                    for (uint32_t q = 0; q < nrep; ++q)
+                        gptr(tabu)[(size_t)u * TS + po + q] = until;
+                    const uint32_t rel = until - tbase;
+                    const uint32_t mark = rel > 253u ? 255u : rel + 1u;
+                    if (mark > ws.tm8[u]) ws.tm8[u] = (uint8_t)mark;
+                }
+            }
+        } else {
+            // 4. apply.  Counts: lanes 0-1 the leaving colour's row and column
+            //    count (-1), lanes 2-3 the entering colour's (+1), as LDS adds on
+            //    the bytes of u32 words (exact: counts stay within 0..n, nothing
+            //    carries), an add of 0 for colour 0.  Lane 0: v's colour, and v's
+            //    eligibility bit cleared (an exact add: v was eligible) unless v
+            //    stays in V_0 u C.  Lane roles are bit masks, not branches.
+            if (lane < 4) {
+                const uint32_t col = (ln_new & (uint32_t)k) | (~ln_new & (uint32_t)old);
+                const uint32_t hb = ((ln_odd & (uint32_t)(cH - ws.H)) |
+                                     (~ln_odd & (uint32_t)(rH - ws.H))) + col;
+                const uint32_t add = col != 0u ? ((ln_new & 2u) - 1u) << ((hb & 3u) * 8u) : 0u;
+                atomicAdd(reinterpret_cast<uint32_t *>(ws.H) + (hb >> 2), add);
+            }
+            if (lane == 0) {
+                ws.S[v] = (uint8_t)k;
+                atomicAdd(&ws.bm[v >> 5], (k == 0 || vC) ? 0u : 0u - (1u << (v & 31)));
+            }
+            PLSE_WAVE_SYNC();
+            // eligibility of the row/column vertices holding the old or new colour:
+            // all reads unconditional, one toggle where it changes
+            int32_t dC = 0;
+            for (int t0 = 0; t0 < deg; t0 += 64) {
+                const int t = t0 + lane;
+                const uint32_t ent = t0 == 0 ? ent0 : (t < deg ? gptr(nb)[t] : 0u);
+                const bool inrow = (ent >> 31) == 0;
+                const int u = (int)(ent & 0xFFFFu), other = (int)((ent >> 16) & 0x7FFFu);
+                const int su = ws.S[u];
+                const uint32_t bw = ws.bm[u >> 5];
+                const int rrow = inrow ? r : other, rcol = inrow ? other : c;
+                const int cu = (int)rowH[rrow * np1 + su] + (int)colH[rcol * np1 + su] - 2;
+                const bool hit = t < deg && su != 0 && (su == old || su == k);
+                const bool was = (bw >> (u & 31)) & 1u;
+                const bool now = cu > 0;
+                const bool flip = hit && (now != was);
+                if (flip) atomicXor(&ws.bm[u >> 5], 1u << (u & 31));
+                dC += (int32_t)__popcll(ballot(flip && now)) - (int32_t)__popcll(ballot(flip && !now));
+            }
+            const int32_t df = (k == 0 ? 1 : 0) - (old == 0 ? 1 : 0);
+            sc.nC += dC + (vC ? 1 : 0) - (old ? 1 : 0);
+            sc.f += df;
+            sc.c += cvk - cvo;
+            sc.F += (int64_t)phi_den * df + (int64_t)phi_num * (cvk - cvo);
+            ucnt.nupd += 2u * (old != 0) + 2u * (k != 0);
+            // tenure T = L + alpha (|V_0| + |C|) after the move; moving v back to
+            // `old` is tabu for T iterations
+            const uint32_t mp = (uint32_t)(sc.f + sc.nC);
+            const uint32_t T = scale32(w0, 10u) + udiv_by(alpha_n * mp, alpha_d, m_alpha);
+            const uint32_t until = itu + 1u + T;
+            pend_tv = (uint32_t)v;
+            pend_tu = until;
+            {
+                // the entry of the last domain colour is repeated over the rest
+                // of its chunk, where the candidate row repeats that colour
+                const uint32_t po = position_in(dmask, old);
+                const uint32_t dv = (uint32_t)(__popcll(((uint64_t)dmask.y << 32) | dmask.x) +
+                                               __popcll(((uint64_t)dmask.w << 32) | dmask.z));
+                const uint32_t nrep = po == dv ? (uint32_t)CH - dv % (uint32_t)CH : 1u;
+                pend_off = (uint32_t)lane < nrep ? (uint32_t)v * (uint32_t)TS + po + (uint32_t)lane
+                                                 : 0xFFFFFFFFu;
+                pend_val = until;
+            }
         }
         PLSE_WAVE_SYNC();
         if (sc.F < sc.Fbest) {
@@ -536,13 +594,13 @@ __device__ void run_phase(const PlitsArgs &a, int phase, int64_t iters, uint32_t
 }
 
 // Greedy conflict removal (Section 3.7): uncolour the vertex with the most
-// conflicts (ties: lowest id) until the colouring is legal.
-__device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Scal &sc,
-                       Cnt &ucnt) {
+// conflicts (ties: lowest id) until the colouring is legal; `from` -> `out`.
+__device__ void repair(const PlitsArgs &a, const uint8_t *from, uint8_t *out, const WaveState &ws,
+                       Scal &sc, Cnt &ucnt) {
     const DevInstance &I = a.I;
     const int lane = lane_id();
     const int n = I.n, nv = I.nv, np1 = n + 1;
-    setup_state(I, out, ws, sc);
+    setup_state(I, from, ws, sc);
     uint8_t *rowH = ws.H, *colH = ws.H + n * np1;
     for (;;) {
         uint32_t lkey = 0u;
@@ -577,7 +635,7 @@ __device__ void repair(const PlitsArgs &a, uint8_t *out, const WaveState &ws, Sc
 
 }  // namespace
 
-template <int CH>
+template <int CH, bool PARTIAL>
 __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
     const PlitsArgs a = arg_of<PlitsArgs>(L);
@@ -623,16 +681,26 @@ __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     uint32_t lane_cands = 0;
     Scal sc;
     const uint32_t slot = (uint32_t)readfirst(ind);
-    // phase 1 from the offspring, phase 2 from phase 1's best (both write
-    // their best into `out`)
-    run_phase<CH>(a, 1, a.P.depth1, slot, (uint32_t)gen, src, out, tabu, ws, sc, ucnt,
-                  lane_cands);
-    run_phase<CH>(a, 2, a.P.depth2, slot, (uint32_t)gen, out, out, tabu, ws, sc, ucnt,
-                  lane_cands);
-    int32_t f_final = sc.fbest;
-    if (sc.cbest > 0) {
-        repair(a, out, ws, sc, ucnt);
-        f_final = sc.f + (int32_t)ucnt.repairs;
+    int32_t f_final;
+    if constexpr (PARTIAL) {
+        // Partial-MPMA (Section 3.7): the offspring repaired into a legal
+        // partial colouring, then PartialCol for the whole depth
+        repair(a, src, out, ws, sc, ucnt);
+        run_phase<CH, 3>(a, a.P.depth1 + a.P.depth2, slot, (uint32_t)gen, out, out, tabu, ws,
+                         sc, ucnt, lane_cands);
+        f_final = sc.fbest;
+    } else {
+        // phase 1 from the offspring, phase 2 from phase 1's best (both write
+        // their best into `out`)
+        run_phase<CH, 1>(a, a.P.depth1, slot, (uint32_t)gen, src, out, tabu, ws, sc, ucnt,
+                         lane_cands);
+        run_phase<CH, 2>(a, a.P.depth2, slot, (uint32_t)gen, out, out, tabu, ws, sc, ucnt,
+                         lane_cands);
+        f_final = sc.fbest;
+        if (sc.cbest > 0) {
+            repair(a, out, out, ws, sc, ucnt);
+            f_final = sc.f + (int32_t)ucnt.repairs;
+        }
     }
     const uint64_t cands = wave_sum_u64(lane_cands);
     const int lane = lane_id();
@@ -653,6 +721,16 @@ __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     if (lane == 0) gptr(a.f_out)[ind] = f_final;
 }
 
+// The PLITS kernel of a chunk size, MPMA or Partial-MPMA; null for other sizes.
+const void *plits_fn(int slots_per_lane, bool partial) {
+    switch (slots_per_lane) {
+        case 2: return partial ? (const void *)plits_kernel<2, true> : (const void *)plits_kernel<2, false>;
+        case 4: return partial ? (const void *)plits_kernel<4, true> : (const void *)plits_kernel<4, false>;
+        case 8: return partial ? (const void *)plits_kernel<8, true> : (const void *)plits_kernel<8, false>;
+        default: return nullptr;
+    }
+}
+
 // Zero a tabu region (a fresh workspace, before the first phase uses it).
 __global__ void fill_zero_kernel(const ArgList L) {
     const FillArgs a = arg_of<FillArgs>(L);
@@ -664,17 +742,15 @@ __global__ void fill_zero_kernel(const ArgList L) {
 }
 
 hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
-                        int slots_per_lane, int waves_per_block, hipStream_t stream) {
+                        int slots_per_lane, int waves_per_block, bool partial,
+                        hipStream_t stream) {
     const int blocks = (p + waves_per_block - 1) / waves_per_block;
     const size_t lds = (size_t)lds_per_wave * waves_per_block;
     const dim3 grid(blocks, count), block(64 * waves_per_block);
-    switch (slots_per_lane) {
-        case 2: hipLaunchKernelGGL(plits_kernel<2>, grid, block, lds, stream, L); break;
-        case 4: hipLaunchKernelGGL(plits_kernel<4>, grid, block, lds, stream, L); break;
-        case 8: hipLaunchKernelGGL(plits_kernel<8>, grid, block, lds, stream, L); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const void *fn = plits_fn(slots_per_lane, partial);
+    if (!fn) return hipErrorInvalidValue;
+    void *args[] = {const_cast<ArgList *>(&L)};
+    return hipLaunchKernel(fn, grid, block, args, lds, stream);
 }
 
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
@@ -684,10 +760,8 @@ hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
 
 // Resident waves per CU of a PLITS launch shape (the runtime's occupancy
 // calculation: registers, LDS and workgroup limits).
-int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave) {
-    const void *fn = slots_per_lane == 2   ? (const void *)plits_kernel<2>
-                     : slots_per_lane == 4 ? (const void *)plits_kernel<4>
-                                           : (const void *)plits_kernel<8>;
+int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial) {
+    const void *fn = plits_fn(slots_per_lane, partial);
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64 * waves_per_block,
                                                      (size_t)lds_per_wave * waves_per_block) !=
@@ -699,9 +773,10 @@ int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave
 }
 
 hipError_t plits_set_lds_limit(int bytes) {
-    hipError_t e = set_dynamic_lds_limit((const void *)plits_kernel<2>, bytes);
-    if (e == hipSuccess) e = set_dynamic_lds_limit((const void *)plits_kernel<4>, bytes);
-    if (e == hipSuccess) e = set_dynamic_lds_limit((const void *)plits_kernel<8>, bytes);
+    hipError_t e = hipSuccess;
+    for (int spl : {2, 4, 8})
+        for (bool partial : {false, true})
+            if (e == hipSuccess) e = set_dynamic_lds_limit(plits_fn(spl, partial), bytes);
     return e;
 }
 

@@ -161,11 +161,14 @@ struct AuxArgs {
 
 // Launch entry points: `L` lists the argument blocks (device addresses) of
 // `count` instances; grid.y = count.
+// partial: Partial-MPMA's search (repair, then PartialCol) instead of PLITS.
 hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
-                        int slots_per_lane, int waves_per_block, hipStream_t stream);
+                        int slots_per_lane, int waves_per_block, bool partial,
+                        hipStream_t stream);
+const void *plits_fn(int slots_per_lane, bool partial);
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream);
 hipError_t plits_set_lds_limit(int bytes);
-int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave);
+int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial);
 hipError_t launch_init(const ArgList &L, int count, int p, size_t lds, hipStream_t stream);
 size_t init_lds_bytes(const DevInstance &I, int pow2);
 hipError_t init_set_lds_limit(int bytes);

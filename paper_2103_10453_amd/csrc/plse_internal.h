@@ -20,6 +20,7 @@ enum Tag : uint32_t {
     TAG_INIT_PICK = 0x02,
     TAG_PLITS1 = 0x11,
     TAG_PLITS2 = 0x12,
+    TAG_PARTIAL = 0x13,
     TAG_SELECT = 0x21,
     TAG_XOVER = 0x31,
     TAG_MATCH = 0x41,
@@ -53,6 +54,7 @@ struct Params {
     int32_t hist_len;
     int32_t crossover;  // 0 AUX (Alg. 5), 1 UX (p_ij = 1/2), 2 none (Section 5.2)
     int32_t matching;   // 0 nearest neighbour (Section 3.5.1), 1 random (Section 5.3)
+    int32_t variant;    // 0 MPMA, 1 Partial-MPMA (Section 3.7)
 };
 
 // Device control block of a solve (one per handle).

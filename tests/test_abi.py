@@ -81,7 +81,8 @@ def test_parameters_and_defaults():
         P.plse_set_param(h, "matching", 1)
         assert P.plse_get_param(h, "crossover") == 2 and P.plse_get_param(h, "matching") == 1
         for key, val in (("nope", 1), ("slots_per_lane", 3), ("nn_history", 65), ("alpha_den", 0),
-                         ("waves_per_block", 3), ("crossover", 3), ("matching", 2)):
+                         ("waves_per_block", 3), ("crossover", 3), ("matching", 2),
+                         ("variant", 2)):
             with pytest.raises(P.PlseError) as e:
                 P.plse_set_param(h, key, val)
             assert e.value.status == P.PLSE_E_PARAM

@@ -119,6 +119,60 @@ def test_plits_from_conflicting_start(torch_cuda, oracle_mod):
         np.testing.assert_array_equal(_np(c1).astype(np.uint64), c1o)
 
 
+# --- Partial-MPMA (Section 3.7) --------------------------------------------------------
+@pytest.mark.parametrize("name,p,depth,spl,random_start", [
+    ("greedy12_60", 37, 1440, 0, True),
+    ("greedy20_50", 65, 4000, 4, True),
+    ("greedy20_50", 40, 4000, 2, False),
+    ("greedy70_70", 9, 6000, 8, True),
+    ("greedy30_80", 33, 9000, 0, True),
+])
+def test_partial_plits_parity(torch_cuda, oracle_mod, name, p, depth, spl, random_start):
+    """Repair of the offspring, then PartialCol: S', f' and every counter equal
+    the oracle's."""
+    g = gen.random_greedy(30, 0.8, 11) if name == "greedy30_80" else _instances()[name]
+    _say(f"partial plits {name} p={p} depth={depth} spl={spl} random={random_start}")
+    s = P.Solver(g, depth=depth, slots_per_lane=spl, variant=1)
+    I = oracle_mod.Instance(g)
+    import torch
+    seed = 313 + p
+    if random_start:
+        vr, vc, off, dom = I.tables()
+        rng = np.random.default_rng(seed)
+        S0 = np.zeros((p, s.stride), dtype=np.uint8)
+        for i in range(p):
+            for v in range(I.nv):
+                choices = [0] + list(dom[off[v]:off[v + 1]])
+                S0[i, v] = choices[rng.integers(0, len(choices))]
+        S0t = torch.from_numpy(S0).cuda()
+        S0o = S0[:, :I.nv]
+    else:
+        S0t, _ = s.stage_init(p, seed)
+        S0o, _ = I.init(seed, p)
+    S1, f1, c1 = s.stage_plits(S0t, 2, seed)
+    torch.cuda.synchronize()
+    S1o, f1o, c1o = I.plits(I.params(depth=depth, variant=oracle_mod.V_PARTIAL), seed, 2,
+                            list(range(p)), S0o)
+    np.testing.assert_array_equal(_np(S1)[:, :I.nv], S1o)
+    np.testing.assert_array_equal(_np(f1), f1o)
+    np.testing.assert_array_equal(_np(c1).astype(np.uint64), c1o)
+
+
+def test_partial_solve_parity(torch_cuda, oracle_mod):
+    """A whole Partial-MPMA run (Section 3.7) equals the oracle's."""
+    g = gen.random_greedy(25, 0.75, 3)
+    _say("partial solve greedy25_75 p=32 G=4")
+    s = P.Solver(g, depth=2500, variant=1)
+    grid, filled = s.solve(32, 4, 55)
+    st = s.stats()
+    I = oracle_mod.Instance(g)
+    r = I.run(I.params(depth=2500, variant=oracle_mod.V_PARTIAL), 32, 4, 55)
+    assert filled == r["filled"]
+    np.testing.assert_array_equal(grid, r["grid"])
+    np.testing.assert_array_equal(st["counters_per_gen"], r["counters"][:r["gens"]])
+    assert gen.is_partial_latin(grid)
+
+
 # --- distances, selection, matching, crossover --------------------------------------
 @pytest.mark.parametrize("name,m", [("planted10", 1), ("planted10", 130), ("greedy20_50", 200),
                                     ("planted33_45", 257), ("greedy70_70", 65)])
