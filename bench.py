@@ -146,7 +146,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n50", choices=["n50", "n70_30", "n70_50", "n70_70",
-                                                         "small", "batch", "served", "lsc"])
+                                                         "n70_80", "small", "batch", "served",
+                                                         "lsc"])
+    ap.add_argument("--variant", type=int, default=0, choices=[0, 1],
+                    help="0 MPMA, 1 Partial-MPMA (repair + PartialCol)")
     ap.add_argument("--instances", type=int, default=256, help="batch: number of instances")
     ap.add_argument("--requests", type=int, default=16, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
@@ -197,12 +200,14 @@ def main():
         r = int(args.workload.split("_")[1]) / 100.0
         w = gen.workload_n70(r)
         desc = f"random-greedy n=70, {int(r * 100)}% prefilled, population 16384, depth 10n^2"
+    if args.variant:
+        desc += ", Partial-MPMA"
     if args.population:
         w["population"] = args.population
     p = w["population"]
     torch.cuda.set_device(0)
     s = plse.Solver(w["grid"], depth=w["depth"], slots_per_lane=args.slots_per_lane,
-                    waves_per_block=args.waves_per_block)
+                    waves_per_block=args.waves_per_block, variant=args.variant)
     s.ensure_workspace(p)
     stream = torch.cuda.current_stream()
 
@@ -230,8 +235,8 @@ def main():
     lds_gbs = (sum(bytes_gen) / max(len(bytes_gen), 1)) / t_mean / 1e9
     traffic = plits_traffic(args.warmup, args.steps, args.workload)
     out = {
-        "metric": "tabu moves/s (n=50, pop 16384)" if args.workload == "n50"
-        else f"tabu moves/s ({args.workload}, pop {p})",
+        "metric": "tabu moves/s (n=50, pop 16384)" if args.workload == "n50" and not args.variant
+        else f"tabu moves/s ({args.workload}{', Partial-MPMA' if args.variant else ''}, pop {p})",
         "value": value,
         "unit": "moves/s",
         "n_gpus": 1,
