@@ -132,16 +132,19 @@ constexpr int kCW = 8;      // words of 32 vertices staged per step
 
 
 // One 64x64 tile (I <= J) per 256-thread workgroup; each thread owns a 4x4
-// block of pairs (rows ty+16i, columns tx+16j).  Both D[I][J] and its mirror
-// are written through an LDS staging tile so that stores are row-contiguous.
+// block of pairs (rows ty+16i, columns tx+16j).  The output tile reuses the
+// operand LDS, so more workgroups fit per CU.  Both D[I][J] and its mirror
+// are written through that LDS tile so that stores are row-contiguous.
 template <int B>
 __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
     const DistArgs a = arg_of<DistArgs>(L);
     if (a.ctl && a.ctl->stop) return;
     constexpr int PITCH = kCW * B + 1;  // odd pitch: rows fall in distinct banks
-    __shared__ uint32_t As[kTile * PITCH];
-    __shared__ uint32_t Bs[kTile * PITCH];
-    __shared__ int16_t Dt[kTile][kTile + 2];
+    constexpr int OPW = 2 * kTile * PITCH;             // operand words
+    constexpr int DTW = kTile * (kTile + 2) / 2;       // output tile words
+    __shared__ uint32_t AB[OPW > DTW ? OPW : DTW];
+    uint32_t *As = AB, *Bs = AB + kTile * PITCH;
+    int16_t(*Dt)[kTile + 2] = reinterpret_cast<int16_t(*)[kTile + 2]>(AB);
     // triangular tile index -> (I, J), I <= J
     const long t = blockIdx.x;
     long J = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -172,6 +175,7 @@ __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
             Bs[row * PITCH + rem] = vb;
         }
         __syncthreads();
+#pragma unroll 1
         for (int wc = 0; wc < nw; ++wc) {
             uint32_t ra[4][B], rb[4][B];
 #pragma unroll
