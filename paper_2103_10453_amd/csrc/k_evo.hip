@@ -351,12 +351,15 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     // memory by select_keys_kernel / sort_*_kernel
     const int off_keys = (nbw * 4 + 15) & ~15;
     uint64_t *K = a.keys_in_lds ? reinterpret_cast<uint64_t *>(lds + off_keys) : a.keys_g;
-    // close lists of the 64 candidates being scanned, staged per block
+    // close lists of the 64 candidates being scanned, staged per block, and
+    // each candidate's lane in the block being scanned (0xFF: not in it)
     uint16_t *adjs = reinterpret_cast<uint16_t *>(lds + off_keys + (a.keys_in_lds ? P2 * 8 : 0));
+    uint8_t *inb = reinterpret_cast<uint8_t *>(adjs + 64 * kAdj);
     if (a.keys_in_lds)
         for (int q = tid; q < (P2 >> 2); q += nthr) select_keys(a, (uint32_t)gen, q, K);
     for (int q = tid; q < nbw; q += nthr) blocked[q] = 0u;
     for (int q = tid; q < m; q += nthr) *gptr(a.pos + q) = -1;
+    for (int q = tid; q < m; q += nthr) inb[q] = 0xFF;
     __syncthreads();
     for (int k = 2; k <= (a.keys_in_lds ? P2 : 1); k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -390,6 +393,53 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
             for (int q = 0; q < (d + 7) / 8; ++q) dst[q] = gload4(src + q);
         }
         PLSE_WAVE_SYNC();
+        if (ballot(valid && d > kAdj) == 0) {
+            // every close list is complete: decide the block in scan order on
+            // 64-bit masks.  mk: the later candidates of this block that this
+            // one's close list holds; bl: the candidates blocked so far.
+            if (valid) inb[x] = (uint8_t)lane;
+            PLSE_WAVE_SYNC();
+            uint64_t mk = 0;
+            for (int q = 0; q < d; ++q) {
+                const uint32_t j = inb[adjs[lane * kAdj + q]];
+                if (j != 0xFFu && (int)j > lane) mk |= 1ull << j;
+            }
+            PLSE_WAVE_SYNC();
+            if (valid) inb[x] = 0xFF;
+            uint64_t bl = ballot(valid && ((blocked[x >> 5] >> (x & 31)) & 1u));
+            const int nvalid = (int)__popcll(ballot(valid));
+            uint64_t accm = 0, rejm = 0;
+            int room = a.p - na;
+            for (int i = 0; i < nvalid; ++i) {
+                if ((bl >> i) & 1ull) {
+                    rejm |= 1ull << i;
+                    continue;
+                }
+                accm |= 1ull << i;
+                const uint32_t lo = readlane_u32((uint32_t)mk, i);
+                const uint32_t hi = readlane_u32((uint32_t)(mk >> 32), i);
+                bl |= ((uint64_t)hi << 32) | lo;
+                if (--room == 0) {
+                    full = true;
+                    break;
+                }
+            }
+            const bool am = (accm >> lane) & 1ull, rm = (rejm >> lane) & 1ull;
+            if (am) *gptr(a.acc + na + (int)rank_below(accm)) = x;
+            if (rm) *gptr(a.rej + nr + (int)rank_below(rejm)) = x;
+            na += (int)__popcll(accm);
+            nr += (int)__popcll(rejm);
+            // accepted candidates block their close lists for later blocks
+            if (am)
+                for (int q = 0; q < d; ++q) {
+                    const int y = adjs[lane * kAdj + q];
+                    atomicOr(&blocked[y >> 5], 1u << (y & 31));
+                }
+            PLSE_WAVE_SYNC();
+            continue;
+        }
+        // a close list longer than kAdj in the block: step from one
+        // unblocked candidate with a non-empty close list to the next
         int pos = 0;
         while (pos < 64) {
             const bool blk = valid && ((blocked[x >> 5] >> (x & 31)) & 1u);
@@ -440,7 +490,8 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
 
 size_t select_lds_bytes(int m, int pow2, bool keys_in_lds) {
     const size_t b = ((size_t)((m + 31) / 32) * 4 + 15) & ~(size_t)15;
-    return b + (keys_in_lds ? (size_t)pow2 * 8 : 0) + (size_t)64 * kAdj * 2;
+    return b + (keys_in_lds ? (size_t)pow2 * 8 : 0) + (size_t)64 * kAdj * 2 +
+           (((size_t)m + 15) & ~(size_t)15);
 }
 
 
