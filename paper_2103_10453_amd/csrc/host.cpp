@@ -36,6 +36,12 @@ int next_pow2(int x) {
 }
 
 // Bits needed for colours 0..n.
+// Distance tiles (64 x 64, I <= J) that lie within P_t (rows 0..p-1).
+long old_tiles(int p) {
+    const long j0 = p / kDistTile;
+    return j0 * (j0 + 1) / 2;
+}
+
 int colour_bits(int n) {
     int b = 0;
     while ((1 << b) <= n) ++b;
@@ -58,8 +64,8 @@ struct ArgBlock {
     PlitsArgs plits;
     InitArgs init;
     BestArgs best;
-    PackArgs pack;
-    DistArgs dist;
+    PackArgs pack, pack_t;  // rows of P' (after the search), of P_t (beside it)
+    DistArgs dist, dist_t;  // tiles involving P', tiles within P_t
     CloseArgs close;
     SelectArgs select;
     GatherArgs gather;
@@ -411,9 +417,18 @@ void build_pipeline_args(plse_instance *h, int p, uint64_t seed) {
                       at<uint8_t>(h, L.Sstar), p, st, h->n * h->n - h->l, h->ub,
                       h->P.stop_at_ub};
     const int W = (h->nv + 31) / 32;
-    A.pack = PackArgs{ctl, S_all, at<uint32_t>(h, L.planes), m, h->nv, st, W, colour_bits(h->n)};
-    const int nt1 = (m + 63) / 64;
-    A.dist = DistArgs{ctl, at<uint32_t>(h, L.planes), at<int16_t>(h, L.D), m, W, m, nt1};
+    // distances among P_t (rows 0..p-1) need nothing from this generation's
+    // searches, so they are packed and computed beside them; the rest after
+    const int B = colour_bits(h->n);
+    // (with no tile within P_t, p < 64, the rest packs all 2p rows)
+    const bool split = old_tiles(p) > 0;
+    A.pack_t = PackArgs{ctl, S_all, at<uint32_t>(h, L.planes), p, h->nv, st, W, B, 0};
+    A.pack = split ? PackArgs{ctl, S_all, at<uint32_t>(h, L.planes), p, h->nv, st, W, B, p}
+                   : PackArgs{ctl, S_all, at<uint32_t>(h, L.planes), m, h->nv, st, W, B, 0};
+    const int nt1 = (m + kDistTile - 1) / kDistTile;
+    A.dist_t = DistArgs{ctl, at<uint32_t>(h, L.planes), at<int16_t>(h, L.D), m, W, m, nt1, 0};
+    A.dist = DistArgs{ctl, at<uint32_t>(h, L.planes), at<int16_t>(h, L.D), m, W, m, nt1,
+                      (int32_t)old_tiles(p)};
     A.close = CloseArgs{ctl, at<int16_t>(h, L.D), at<int32_t>(h, L.deg), at<uint16_t>(h, L.adj),
                         m, m, h->nv, h->P.spacing};
     A.select = make_select(h, p, 0, seed, ctl, f_all, at<int16_t>(h, L.D), m,
@@ -480,8 +495,19 @@ struct Session {
     std::vector<hipEvent_t> ev;                   // 3 per generation
     std::vector<hipStream_t> side;                // groups 1.. of a generation
     std::vector<hipEvent_t> fork;                 // 1 + one per side stream
+    // distances among P_t, beside the searches: graph, stream, fork / join
+    hipGraphExec_t dold = nullptr;
+    hipStream_t dstream = nullptr;
+    hipEvent_t dfork = nullptr, djoin = nullptr;
 
     ~Session() {
+        if (dstream) {
+            (void)hipStreamSynchronize(dstream);
+            (void)hipStreamDestroy(dstream);
+        }
+        if (dold) (void)hipGraphExecDestroy(dold);
+        if (dfork) (void)hipEventDestroy(dfork);
+        if (djoin) (void)hipEventDestroy(djoin);
         if (ls) (void)hipGraphExecDestroy(ls);
         if (rest) (void)hipGraphExecDestroy(rest);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -526,14 +552,13 @@ int enqueue_local_search(Session &S, hipStream_t s) {
     return PLSE_OK;
 }
 
-int enqueue_rest(Session &S, hipStream_t s) {
-    const int p = S.p, m = 2 * p;
-    RC_TRY(launch_over(S.hs, &ArgBlock::best,
-                       [&](const ArgList &L, int c) { return launch_best(L, c, s); }));
+// Bit planes of one half of P^all and the distance tiles of one tile range.
+int enqueue_pack_dist(Session &S, PackArgs ArgBlock::*pk, DistArgs ArgBlock::*dt, int rows,
+                      long tiles, hipStream_t s) {
     size_t pack_threads = 0;
     for (plse_instance *h : S.hs)
-        pack_threads = std::max(pack_threads, (size_t)m * ((h->nv + 31) / 32));
-    RC_TRY(launch_over(S.hs, &ArgBlock::pack, [&](const ArgList &L, int c) {
+        pack_threads = std::max(pack_threads, (size_t)rows * ((h->nv + 31) / 32));
+    RC_TRY(launch_over(S.hs, pk, [&](const ArgList &L, int c) {
         return launch_pack(L, c, pack_threads, s);
     }));
     for (int B = 1; B <= 7; ++B) {
@@ -541,9 +566,25 @@ int enqueue_rest(Session &S, hipStream_t s) {
         for (plse_instance *h : S.hs)
             if (colour_bits(h->n) == B) g.push_back(h);
         if (g.empty()) continue;
-        RC_TRY(launch_over(g, &ArgBlock::dist,
-                           [&](const ArgList &L, int c) { return launch_dist(L, c, m, B, s); }));
+        RC_TRY(launch_over(g, dt, [&](const ArgList &L, int c) {
+            return launch_dist(L, c, tiles, B, s);
+        }));
     }
+    return PLSE_OK;
+}
+
+// Distances among P_t, beside the generation's searches.
+int enqueue_old_dist(Session &S, hipStream_t s) {
+    return enqueue_pack_dist(S, &ArgBlock::pack_t, &ArgBlock::dist_t, S.p, old_tiles(S.p), s);
+}
+
+int enqueue_rest(Session &S, hipStream_t s) {
+    const int p = S.p, m = 2 * p;
+    RC_TRY(launch_over(S.hs, &ArgBlock::best,
+                       [&](const ArgList &L, int c) { return launch_best(L, c, s); }));
+    const long nt1 = (m + kDistTile - 1) / kDistTile;
+    RC_TRY(enqueue_pack_dist(S, &ArgBlock::pack, &ArgBlock::dist, old_tiles(p) > 0 ? p : m,
+                             nt1 * (nt1 + 1) / 2 - old_tiles(p), s));
     RC_TRY(launch_over(S.hs, &ArgBlock::close,
                        [&](const ArgList &L, int c) { return launch_close(L, c, m, s); }));
     const size_t sl = select_lds(S.hs[0], p);
@@ -667,6 +708,12 @@ int session_begin(Session &S, const uint64_t *seeds, hipStream_t s) {
     if (S.groups.size() == 1)
         RC_TRY(capture([&](hipStream_t cs) { return enqueue_local_search(S, cs); }, &S.ls));
     RC_TRY(capture([&](hipStream_t cs) { return enqueue_rest(S, cs); }, &S.rest));
+    if (old_tiles(S.p) > 0) {
+        RC_TRY(capture([&](hipStream_t cs) { return enqueue_old_dist(S, cs); }, &S.dold));
+        HIP_TRY(hipStreamCreateWithFlags(&S.dstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&S.dfork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&S.djoin, hipEventDisableTiming));
+    }
     S.steps = 0;
     return PLSE_OK;
 }
@@ -680,12 +727,21 @@ int session_step(Session &S, int generations, hipStream_t s) {
     }
     for (int g = 0; g < generations; ++g) {
         const size_t k = 3 * (size_t)(S.steps + g);
+        if (S.dold) {
+            // P_t is final (previous generation's update, or P_1): its
+            // distances run beside the searches, joined before the rest
+            HIP_TRY(hipEventRecord(S.dfork, s));
+            HIP_TRY(hipStreamWaitEvent(S.dstream, S.dfork, 0));
+            HIP_TRY(hipGraphLaunch(S.dold, S.dstream));
+            HIP_TRY(hipEventRecord(S.djoin, S.dstream));
+        }
         HIP_TRY(hipEventRecord(S.ev[k], s));
         if (S.ls)
             HIP_TRY(hipGraphLaunch(S.ls, s));
         else
             RC_TRY(enqueue_local_search(S, s));
         HIP_TRY(hipEventRecord(S.ev[k + 1], s));
+        if (S.dold) HIP_TRY(hipStreamWaitEvent(s, S.djoin, 0));
         HIP_TRY(hipGraphLaunch(S.rest, s));
         HIP_TRY(hipEventRecord(S.ev[k + 2], s));
     }
@@ -1195,11 +1251,12 @@ int plse_stage_distances(plse_handle h, int32_t m, void *stream, const uint8_t *
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     RC_TRY(stage_prepare(h, std::max(2, (m + 1) / 2), s));
     const int W = (h->nv + 31) / 32, B = colour_bits(h->n);
-    h->args.pack = PackArgs{nullptr, S, at<uint32_t>(h, h->L.planes), m, h->nv, h->stride, W, B};
-    h->args.dist = DistArgs{nullptr, at<uint32_t>(h, h->L.planes), D, m, W, m, (m + 63) / 64};
+    h->args.pack = PackArgs{nullptr, S, at<uint32_t>(h, h->L.planes), m, h->nv, h->stride, W, B, 0};
+    const int nt1 = (m + kDistTile - 1) / kDistTile;
+    h->args.dist = DistArgs{nullptr, at<uint32_t>(h, h->L.planes), D, m, W, m, nt1, 0};
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_pack(single(h, &ArgBlock::pack), 1, (size_t)m * W, s));
-    HIP_TRY(launch_dist(single(h, &ArgBlock::dist), 1, m, B, s));
+    HIP_TRY(launch_dist(single(h, &ArgBlock::dist), 1, (long)nt1 * (nt1 + 1) / 2, B, s));
     return PLSE_OK;
 }
 

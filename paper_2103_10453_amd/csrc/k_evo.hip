@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ArgList L) {
     if (a.ctl && a.ctl->stop) return;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)a.m * a.W) return;
-    const int x = (int)(t / a.W), w = (int)(t % a.W);
+    const int x = a.row0 + (int)(t / a.W), w = (int)(t % a.W);
     const uint8_t *row = a.S + (size_t)x * a.stride;
     uint32_t pl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int v0 = w * 32;
@@ -123,11 +123,11 @@ __global__ __launch_bounds__(256) void pack_kernel(const ArgList L) {
 #pragma unroll
         for (int b = 0; b < 8; ++b) pl[b] |= ((s >> b) & 1u) << (v - v0);
     }
-    uint32_t *dst = a.planes + t * a.B;
+    uint32_t *dst = a.planes + ((size_t)x * a.W + w) * a.B;
     for (int b = 0; b < a.B; ++b) dst[b] = pl[b];
 }
 
-constexpr int kTile = 64;   // rows and columns per distance tile
+constexpr int kTile = kDistTile;  // rows and columns per distance tile
 constexpr int kCW = 8;      // words of 32 vertices staged per step
 
 
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
     uint32_t *As = AB, *Bs = AB + kTile * PITCH;
     int16_t(*Dt)[kTile + 2] = reinterpret_cast<int16_t(*)[kTile + 2]>(AB);
     // triangular tile index -> (I, J), I <= J
-    const long t = blockIdx.x;
+    const long t = (long)blockIdx.x + a.tile0;
     long J = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((J + 1) * (J + 2) / 2 <= t) ++J;
     while (J * (J + 1) / 2 > t) --J;
@@ -741,9 +741,9 @@ hipError_t launch_pack(const ArgList &L, int count, size_t max_threads, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_dist(const ArgList &L, int count, int m, int B, hipStream_t stream) {
-    const int nt1 = (m + kTile - 1) / kTile;
-    const dim3 grid((unsigned)((long)nt1 * (nt1 + 1) / 2), count);
+hipError_t launch_dist(const ArgList &L, int count, long tiles, int B, hipStream_t stream) {
+    if (tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)tiles, count);
     switch (B) {
 #define PLSE_DIST_CASE(b) \
     case b: hipLaunchKernelGGL(dist_kernel<b>, grid, dim3(256), 0, stream, L); break;

@@ -72,17 +72,21 @@ struct BestArgs {
 
 struct PackArgs {
     const Ctl *ctl;
-    const uint8_t *S;        // [m][stride]
-    uint32_t *planes;        // [m][W][B]
-    int32_t m, nv, stride, W, B;
+    const uint8_t *S;        // [rows][stride]
+    uint32_t *planes;        // [rows][W][B]
+    int32_t m, nv, stride, W, B;  // m: rows packed, from row row0
+    int32_t row0;
 };
 
 struct DistArgs {
     const Ctl *ctl;
     const uint32_t *planes;  // [m][W][B]
     int16_t *D;              // [m][ld]
-    int32_t m, W, ld, ntiles;
+    int32_t m, W, ld, ntiles;  // ntiles: per side (ceil(m / kDistTile))
+    int32_t tile0;             // first triangular tile index of the launch
 };
+
+constexpr int kDistTile = 64;  // rows and columns per distance tile
 
 struct CloseArgs {
     const Ctl *ctl;
@@ -174,7 +178,8 @@ size_t init_lds_bytes(const DevInstance &I, int pow2);
 hipError_t init_set_lds_limit(int bytes);
 hipError_t launch_best(const ArgList &L, int count, hipStream_t stream);
 hipError_t launch_pack(const ArgList &L, int count, size_t max_threads, hipStream_t stream);
-hipError_t launch_dist(const ArgList &L, int count, int m, int B, hipStream_t stream);
+// tiles: triangular tiles (I <= J) of the launch, from the arg block's tile0
+hipError_t launch_dist(const ArgList &L, int count, long tiles, int B, hipStream_t stream);
 hipError_t launch_close(const ArgList &L, int count, int m, hipStream_t stream);
 hipError_t launch_select(const ArgList &L, int count, size_t lds, int pow2, bool keys_in_lds,
                          hipStream_t stream);
