@@ -55,7 +55,7 @@ struct WaveState {
     uint8_t *tm8;      // [|V|] 0: no tabu entry this phase; 1: entries, all expired;
                        // m in 2..254: latest expiry = base + m - 1; 255: treat as live
     uint16_t *stage;   // [64] the eligible vertices being dealt
-    uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16
+    uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16 | live << 31
     uint16_t *hk;      // [n+1] colour halves of the iteration's tie values
     uint32_t *planes;  // [B][W] bit b of floor(|D*(v)| / CH) (chunks per row - 1)
     int nplanes;
@@ -350,20 +350,32 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
                     PLSE_WAVE_SYNC();
                 }
                 const uint32_t e = g + (uint32_t)lane;
-                uint32_t v = 0u, nch = 0u;
+                uint32_t v = 0u, nch = 0u, ent = 0u;
                 if (e < m) {
                     v = ws.stage[lane];
-                    uint32_t code = 0u;
+                    // chunk count and liveness of v, read together: planes 0
+                    // and 1 (or 0 twice), further planes only when present
+                    const int vw = (int)(v >> 5);
+                    const bool p0ok = ws.nplanes > 0, p1ok = ws.nplanes > 1;
+                    const uint32_t q0 = p0ok ? ws.planes[vw] : 0u;
+                    const uint32_t q1 = p1ok ? ws.planes[W + vw] : 0u;
+                    const uint32_t tm = ws.tm8[v];
+                    uint32_t code = ((q0 >> (v & 31u)) & 1u) | (((q1 >> (v & 31u)) & 1u) << 1);
+                    if (ws.nplanes > 2) {
 #pragma unroll
-                    for (int b = 0; b < 6; ++b)
-                        if (b < ws.nplanes)
-                            code |= ((ws.planes[b * W + (int)(v >> 5)] >> (v & 31u)) & 1u) << b;
+                        for (int b = 2; b < 6; ++b)
+                            if (b < ws.nplanes)
+                                code |= ((ws.planes[b * W + vw] >> (v & 31u)) & 1u) << b;
+                    }
                     nch = code + 1u;  // ceil((d + 1) / CH)
+                    // a vertex not live has no tabu move this iteration
+                    const bool live = tm == 255u || tm > itu - tbase + 1u;
+                    ent = v | ((uint32_t)live << 31);
                 }
                 uint32_t total;
                 const uint32_t at = tail + wave_excl_scan_dpp(nch, &total);
 #pragma unroll 1
-                for (uint32_t t = 0; t < nch; ++t) ws.ring[at + t] = v | (t << 16);
+                for (uint32_t t = 0; t < nch; ++t) ws.ring[at + t] = ent | (t << 16);
                 tail += total;
                 g += 64u;
                 PLSE_WAVE_SYNC();
@@ -372,12 +384,12 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
             const uint32_t x = head + (uint32_t)lane;
             head = min(head + 64u, tail);
             if (x < tail) {
+                // ring entry: vertex | chunk index << 16 | live << 31
                 const uint32_t ent = ws.ring[x];
                 const int v = (int)(ent & 0xFFFFu);
-                const int p0 = (int)(ent >> 16) * CH;
+                const int p0 = (int)((ent >> 16) & 0x7FFFu) * CH;
+                const bool live = (ent >> 31) != 0u;
                 const int s = ws.S[v];
-                const uint32_t tm = ws.tm8[v];
-                const bool live = tm == 255u || tm > itu - tbase + 1u;
                 const uint32_t vi = gptr(I.vinfo)[v];
                 const auto cw = Chunk<CH>::colours(I.cand + (size_t)v * TS + p0);
                 uint32_t tv[CH];
