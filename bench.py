@@ -255,7 +255,8 @@ def main():
                    "waves_per_block": int(s.get_param("waves_per_block"))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "plits_kernel<%d>" % int(s.get_param("slots_per_lane")),
+                     "kernel": "plits_kernel<%d, %s>" % (int(s.get_param("slots_per_lane")),
+                                                          "true" if args.variant else "false"),
                      "hbm_gbs": (traffic / t_mean / 1e9) if traffic else None,
                      "hbm_frac": (traffic / t_mean / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "lds_state_gbs": lds_gbs, "lds_state_frac": lds_gbs / LDS_PEAK_GBS},
