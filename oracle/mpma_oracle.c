@@ -756,6 +756,7 @@ int32_t orc_run(const void *h, const int64_t *P, int32_t p, int32_t G, uint64_t 
     memcpy(Soff, Sall, (size_t)p * snv);
 
     int32_t fstar = INT32_MAX, gens = 0;
+    uint64_t iters_total = 0;
     for (int g = 1; g <= G; g++) {
         gens = g;
         /* local search on every offspring, in parallel */
@@ -775,6 +776,9 @@ int32_t orc_run(const void *h, const int64_t *P, int32_t p, int32_t G, uint64_t 
         }
         best_f_gen[g - 1] = fstar;
         if (P[ORC_P_STOP_AT_UB] && n * n - I->l - fstar == I->ub) break;
+        /* iteration budget (Section 4.2): checked once per generation */
+        iters_total += counters_gen[(size_t)(g - 1) * ORC_NCOUNTERS + 0];
+        if (P[ORC_P_MAX_ITERS] > 0 && iters_total >= (uint64_t)P[ORC_P_MAX_ITERS]) break;
 
         /* distances over P^all, population update, new uids */
         orc_distances(nv, m, Sall, m, Sall, Dall);

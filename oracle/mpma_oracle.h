@@ -30,7 +30,10 @@
  *                  half the differing positions (binomial bound); no
  *                  crossover copies the first parent exactly.
  *   orc_run        filled <= UB; planted instances complete; brute-force
- *                  optimum on tiny grids.
+ *                  optimum on tiny grids; with an iteration cap, the stop
+ *                  generation is the first whose cumulative count reaches the
+ *                  cap (fixed per-generation count on a hard instance) and the
+ *                  capped run is a prefix of the uncapped one.
  */
 #ifndef MPMA_ORACLE_H
 #define MPMA_ORACLE_H
@@ -55,6 +58,9 @@ enum {
     ORC_P_CROSSOVER,    /* ORC_X_*: AUX (Alg. 5), UX or none (Section 5.2)       */
     ORC_P_MATCHING,     /* ORC_M_*: nearest neighbour (3.5.1) or random (5.3)    */
     ORC_P_VARIANT,      /* ORC_V_*: MPMA or Partial-MPMA (Section 3.7)           */
+    ORC_P_MAX_ITERS,    /* > 0: stop after the generation whose cumulative tabu  */
+                        /* iterations (whole population) reach this cap (the     */
+                        /* iteration budget of Section 4.2); 0: no cap           */
     ORC_NPARAMS
 };
 

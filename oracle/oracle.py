@@ -15,9 +15,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-NPARAMS = 13
+NPARAMS = 14
 P_DEPTH1, P_DEPTH2, P_ALPHA_NUM, P_ALPHA_DEN, P_BETA_NUM, P_BETA_DEN, P_SPACING, \
-    P_STOP_AT_UB, P_HIST, P_PARANOID, P_CROSSOVER, P_MATCHING, P_VARIANT = range(NPARAMS)
+    P_STOP_AT_UB, P_HIST, P_PARANOID, P_CROSSOVER, P_MATCHING, P_VARIANT, \
+    P_MAX_ITERS = range(NPARAMS)
 X_AUX, X_UX, X_NONE = 0, 1, 2        # crossover variants (Section 3.5.2, Section 5.2)
 M_NEAREST, M_RANDOM = 0, 1           # matching variants (Section 3.5.1, Section 5.3)
 V_MPMA, V_PARTIAL = 0, 1             # MPMA, Partial-MPMA (Section 3.7)
@@ -83,7 +84,8 @@ def _ptr(a: np.ndarray):
 
 def default_params(nv: int, n: int, depth: int | None = None, stop_at_ub: bool = False,
                    paranoid: bool = False, crossover: int = X_AUX,
-                   matching: int = M_NEAREST, variant: int = V_MPMA) -> np.ndarray:
+                   matching: int = M_NEAREST, variant: int = V_MPMA,
+                   max_iterations: int = 0) -> np.ndarray:
     """Paper defaults (Table 1, Section 3.3) with an optional total depth.
 
     With a depth d, phase 2 keeps its 2|V| iterations and phase 1 gets the rest.
@@ -103,6 +105,7 @@ def default_params(nv: int, n: int, depth: int | None = None, stop_at_ub: bool =
     P[P_CROSSOVER] = int(crossover)
     P[P_MATCHING] = int(matching)
     P[P_VARIANT] = int(variant)
+    P[P_MAX_ITERS] = int(max_iterations)
     return P
 
 

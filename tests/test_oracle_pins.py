@@ -503,3 +503,47 @@ def test_run_stop_at_ub_and_determinism(oracle_mod):
     assert r1["gens"] == 1 and r1["filled"] == 100
     assert np.array_equal(r1["counters"], r2["counters"])
     assert np.array_equal(r1["grid"], r2["grid"])
+
+
+# --- iteration budget (Section 4.2) --------------------------------------------------------
+def test_run_iteration_cap_on_a_hard_instance(oracle_mod):
+    """On an instance whose bound is out of reach no individual ends a phase
+    early, so each generation runs exactly p * depth iterations and a cap C
+    stops the run after generation ceil(C / (p * depth)); the capped run is the
+    run with that many generations."""
+    g = gen.random_greedy(12, 0.6, 5)
+    I = oracle_mod.Instance(g)
+    p, depth, G, seed = 8, 1440, 6, 77
+    full = I.run(I.params(depth=depth), p, G, seed)
+    assert full["filled"] < I.ub
+    assert np.all(full["counters"][:, 0] == p * depth)
+    per = p * depth
+    for cap, stop in ((1, 1), (per, 1), (per + 1, 2), (3 * per - 1, 3), (3 * per, 3),
+                      (G * per + 5, G)):
+        r = I.run(I.params(depth=depth, max_iterations=cap), p, G, seed)
+        assert r["gens"] == stop, (cap, r["gens"])
+        short = I.run(I.params(depth=depth), p, stop, seed)
+        assert r["filled"] == short["filled"]
+        np.testing.assert_array_equal(r["grid"], short["grid"])
+        np.testing.assert_array_equal(r["best_f"][:stop], full["best_f"][:stop])
+        np.testing.assert_array_equal(r["counters"][:stop], full["counters"][:stop])
+        assert np.all(r["counters"][stop:] == 0)
+
+
+def test_run_iteration_cap_with_varying_generation_counts(oracle_mod):
+    """Where individuals finish early the per-generation counts vary; the run
+    stops at the first generation whose cumulative count reaches the cap."""
+    g = gen.random_greedy(20, 0.5, 7)
+    I = oracle_mod.Instance(g)
+    p, depth, G, seed = 8, 4000, 6, 77
+    full = I.run(I.params(depth=depth), p, G, seed)
+    cum = np.cumsum(full["counters"][:, 0].astype(np.int64))
+    assert len(set(full["counters"][:, 0].tolist())) > 1
+    for k in range(G):
+        for cap in (int(cum[k]), int(cum[k]) - 1):
+            if cap <= 0:
+                continue
+            r = I.run(I.params(depth=depth, max_iterations=cap), p, G, seed)
+            stop = 1 + int(np.argmax(cum >= cap))
+            assert r["gens"] == stop
+            np.testing.assert_array_equal(r["counters"][:stop], full["counters"][:stop])
