@@ -235,6 +235,35 @@ __global__ __launch_bounds__(256) void close_kernel(const ArgList L) {
     const int lane = lane_id();
     const int16_t *row = a.D + (size_t)x * a.ld;
     uint32_t cnt = 0;
+    if ((a.ld & 7) == 0 && (a.m & 7) == 0) {
+        // eight distances per lane and load (16-byte rows of D), close list
+        // still in ascending order: lanes in order, then the lane's eight
+        for (int y0 = 0; y0 < a.m; y0 += 512) {
+            const int yb = y0 + lane * 8;
+            uint32_t fl = 0u;
+            if (yb < a.m) {
+                const u32x4 q = gload4(reinterpret_cast<const u32x4 *>(row + yb));
+                const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int16_t d = (int16_t)((w[t >> 1] >> (16 * (t & 1))) & 0xFFFFu);
+                    const bool cl = (yb + t != x) && (a.spacing * (int64_t)d <= (int64_t)a.nv);
+                    fl |= (uint32_t)cl << t;
+                }
+            }
+            uint32_t total;
+            uint32_t pos = cnt + wave_excl_scan_dpp((uint32_t)__popc(fl), &total);
+            while (fl) {
+                const int t = __ffs(fl) - 1;
+                fl &= fl - 1u;
+                if (pos < (uint32_t)kAdj) *gptr(a.adj + (size_t)x * kAdj + pos) = (uint16_t)(yb + t);
+                ++pos;
+            }
+            cnt += total;
+        }
+        if (lane == 0) *gptr(a.deg + x) = (int32_t)cnt;
+        return;
+    }
     for (int y0 = 0; y0 < a.m; y0 += 64) {
         const int y = y0 + lane;
         const bool cl = (y < a.m) && (y != x) && (a.spacing * (int64_t)row[y] <= (int64_t)a.nv);
