@@ -49,7 +49,8 @@ typedef struct {
     int32_t generations_run;      /* <= requested generations (UB stop)         */
     int32_t best_f;               /* uncoloured vertices of S*                  */
     int32_t best_generation;      /* generation in which S* was found           */
-    int32_t reserved;
+    int32_t stop_reason;          /* 0 all generations run, 1 bound reached     */
+                                  /* (stop_at_ub), 2 iteration budget spent     */
     uint64_t totals[PLSE_NCOUNTERS];
 } plse_stats;
 
@@ -92,6 +93,10 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *   "beta_num", "beta_den"     AUX beta (20/1, Eq. 9)
  *   "spacing"     minimum spacing factor gamma of Section 3.4 (10)
  *   "stop_at_ub"  1: stop after the generation whose best reaches the bound
+ *   "max_iterations"  > 0: iteration budget of the run (Section 4.3 caps each
+ *                 run at a total number of tabu iterations): the run stops
+ *                 after the first generation at whose end the population's
+ *                 cumulative iteration count reaches the budget; 0: none
  *   "nn_history"  partner-history length, 0..64 (64)
  *   "crossover"   0 AUX (Alg. 5, default), 1 UX (p_ij fixed at 1/2, Section
  *                 3.5.2), 2 none: the offspring copies its first parent
@@ -160,6 +165,25 @@ int plse_solve(plse_handle h, int32_t population, int32_t generations, uint64_t 
 int plse_begin(plse_handle h, int32_t population, uint64_t seed, void *stream);
 int plse_step(plse_handle h, int32_t generations, void *stream);
 int plse_end(plse_handle h, void *stream, int8_t *best_grid, int32_t *filled);
+
+/*
+ * plse_peek -- progress of the open session: waits for `stream` (so for
+ * every generation stepped so far), then reports the generations run, the
+ * best f, the generation that found it, the population's cumulative tabu
+ * iterations and the stop reason (as in plse_stats; a stopped run ignores
+ * further steps).  For callers that stop on a wall-clock budget between
+ * plse_step calls, as the time-limited runs of Section 5.1.  The session
+ * stays open.  Errors: PLSE_E_ARG (null, no open session), PLSE_E_BUSY,
+ * PLSE_E_HIP.
+ */
+typedef struct {
+    int32_t generations_run;
+    int32_t best_f;               /* INT32_MAX before the first generation ends */
+    int32_t best_generation;
+    int32_t stop_reason;
+    uint64_t iterations;
+} plse_progress;
+int plse_peek(plse_handle h, void *stream, plse_progress *out);
 
 /*
  * plse_solve_batch -- plse_solve on `count` instances at once.
@@ -250,9 +274,11 @@ int plse_stage_aux(plse_handle h, int32_t population, int32_t gen, uint64_t seed
  * stream of its own, with up to two generations of Alg. 2 enqueued ahead, so
  * requests that arrive while others run share the device with them and none
  * waits for another's generations; a finished request's workspace returns
- * to the arena.  Each result is identical to plse_solve of the same
- * instance, parameters, population, generations and seed, whatever else is
- * resident.
+ * to the arena.  A run that stops before its last generation (the bound with
+ * stop_at_ub, or its iteration budget) leaves the device at the end of the
+ * generation that stopped it, instead of stepping through the rest.  Each
+ * result is identical to plse_solve of the same instance, parameters,
+ * population, generations and seed, whatever else is resident.
  *
  * plse_server_create: device_ptr/hbm_budget_bytes the arena (256-byte
  *   aligned, caller-owned, must outlive the server); max_slots >= 1; stream

@@ -776,7 +776,7 @@ int32_t orc_run(const void *h, const int64_t *P, int32_t p, int32_t G, uint64_t 
         }
         best_f_gen[g - 1] = fstar;
         if (P[ORC_P_STOP_AT_UB] && n * n - I->l - fstar == I->ub) break;
-        /* iteration budget (Section 4.2): checked once per generation */
+        /* iteration budget (Section 4.3): checked once per generation */
         iters_total += counters_gen[(size_t)(g - 1) * ORC_NCOUNTERS + 0];
         if (P[ORC_P_MAX_ITERS] > 0 && iters_total >= (uint64_t)P[ORC_P_MAX_ITERS]) break;
 

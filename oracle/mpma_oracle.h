@@ -60,7 +60,7 @@ enum {
     ORC_P_VARIANT,      /* ORC_V_*: MPMA or Partial-MPMA (Section 3.7)           */
     ORC_P_MAX_ITERS,    /* > 0: stop after the generation whose cumulative tabu  */
                         /* iterations (whole population) reach this cap (the     */
-                        /* iteration budget of Section 4.2); 0: no cap           */
+                        /* iteration budget of Section 4.3); 0: no cap           */
     ORC_NPARAMS
 };
 

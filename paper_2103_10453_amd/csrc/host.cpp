@@ -415,7 +415,7 @@ void build_pipeline_args(plse_instance *h, int p, uint64_t seed) {
                          at<uint64_t>(h, L.cnt), ctl);
     A.best = BestArgs{ctl, at<GenStat>(h, L.stats), f_all + p, S_new, at<uint64_t>(h, L.cnt),
                       at<uint8_t>(h, L.Sstar), p, st, h->n * h->n - h->l, h->ub,
-                      h->P.stop_at_ub};
+                      h->P.stop_at_ub, h->P.max_iters};
     const int W = (h->nv + 31) / 32;
     // distances among P_t (rows 0..p-1) need nothing from this generation's
     // searches, so they are packed and computed beside them; the rest after
@@ -499,8 +499,16 @@ struct Session {
     hipGraphExec_t dold = nullptr;
     hipStream_t dstream = nullptr;
     hipEvent_t dfork = nullptr, djoin = nullptr;
+    // pinned host copies of the (single) instance's stop flag when set: the
+    // flag after generation index gi (0-based) lands in stop_host[gi %
+    // kStopRing] before that generation's end event (serving: retire stopped
+    // runs early).  A reader of generation gi's slot must have fewer than
+    // kStopRing generations enqueued beyond gi.
+    static constexpr int kStopRing = 8;
+    int32_t *stop_host = nullptr;
 
     ~Session() {
+        if (stop_host) (void)hipHostFree(stop_host);
         if (dstream) {
             (void)hipStreamSynchronize(dstream);
             (void)hipStreamDestroy(dstream);
@@ -743,6 +751,12 @@ int session_step(Session &S, int generations, hipStream_t s) {
         HIP_TRY(hipEventRecord(S.ev[k + 1], s));
         if (S.dold) HIP_TRY(hipStreamWaitEvent(s, S.djoin, 0));
         HIP_TRY(hipGraphLaunch(S.rest, s));
+        if (S.stop_host) {
+            plse_instance *h = S.hs[0];
+            HIP_TRY(hipMemcpyAsync(S.stop_host + (S.steps + g) % Session::kStopRing,
+                                   &at<Ctl>(h, h->L.ctl)->stop, sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+        }
         HIP_TRY(hipEventRecord(S.ev[k + 2], s));
     }
     S.steps += generations;
@@ -789,6 +803,7 @@ int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &o
         ls.generations_run = gens;
         ls.best_f = ctl[i].fstar;
         ls.best_generation = ctl[i].best_gen;
+        ls.stop_reason = ctl[i].stop_reason;
         h->ms_plits = tp;
         h->ms_rest = tr;
         // best grid: prefilled cells plus S* on the vertices
@@ -947,6 +962,7 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
     h->P.beta_den = 1;
     h->P.spacing = 10;
     h->P.stop_at_ub = 0;
+    h->P.max_iters = 0;  // no iteration budget
     h->P.hist_len = kHist;
     h->P.crossover = 0;  // AUX
     h->P.matching = 0;   // nearest neighbour
@@ -1012,6 +1028,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "stop_at_ub") {
         if (v != 0 && v != 1) return PLSE_E_PARAM;
         P.stop_at_ub = (int32_t)v;
+    } else if (k == "max_iterations") {
+        if (v < 0) return PLSE_E_PARAM;
+        P.max_iters = v;
     } else if (k == "nn_history") {
         if (v < 0 || v > kHist) return PLSE_E_PARAM;
         P.hist_len = (int32_t)v;
@@ -1055,6 +1074,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "beta_den") *v = P.beta_den;
     else if (k == "spacing") *v = P.spacing;
     else if (k == "stop_at_ub") *v = P.stop_at_ub;
+    else if (k == "max_iterations") *v = P.max_iters;
     else if (k == "nn_history") *v = P.hist_len;
     else if (k == "crossover") *v = P.crossover;
     else if (k == "matching") *v = P.matching;
@@ -1118,6 +1138,23 @@ int plse_end(plse_handle h, void *stream, int8_t *best_grid, int32_t *filled) {
     const int rc = session_end(*h->own, reinterpret_cast<hipStream_t>(stream), {h}, grids, filled);
     drop_session(h);
     return rc;
+}
+
+int plse_peek(plse_handle h, void *stream, plse_progress *out) {
+    if (!h || !out) return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok) return PLSE_E_BUSY;
+    if (!h->in_session || !h->own) return PLSE_E_ARG;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, at<Ctl>(h, h->L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out->generations_run = c.gens_run;
+    out->best_f = c.fstar;
+    out->best_generation = c.best_gen;
+    out->stop_reason = c.stop_reason;
+    out->iterations = c.iters;
+    return PLSE_OK;
 }
 
 int plse_solve(plse_handle h, int32_t p, int32_t G, uint64_t seed, void *stream,
@@ -1366,6 +1403,7 @@ int collect(Request &r, hipStream_t s) {
     h->last.generations_run = gens;
     h->last.best_f = c.fstar;
     h->last.best_generation = c.best_gen;
+    h->last.stop_reason = c.stop_reason;
     r.best_gen = c.best_gen;
     r.moves = h->last.totals[C_MOVES];
     const int n = h->n;
@@ -1458,15 +1496,18 @@ struct plse_server_s {
         r->S = new Session();
         r->S->hs = {r->h};
         r->S->p = r->p;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&r->S->stop_host),
+                              sizeof(int32_t) * Session::kStopRing));
+        for (int q = 0; q < Session::kStopRing; ++q) r->S->stop_host[q] = 0;
         return session_begin(*r->S, &r->seed, r->st);
     }
 
-    // Session and stream of a request whose stream has drained.
+    // Session and stream of a request (the stream drains first).
     void retire(Request *r) {
+        if (r->st) (void)hipStreamSynchronize(r->st);
         delete r->S;
         r->S = nullptr;
         if (r->st) {
-            (void)hipStreamSynchronize(r->st);
             (void)hipStreamDestroy(r->st);
             r->st = nullptr;
         }
@@ -1482,6 +1523,7 @@ struct plse_server_s {
 void plse_server_s::loop() {
     (void)hipSetDevice(device);
     constexpr int kAhead = 2;
+    static_assert(kAhead < Session::kStopRing, "stop flags of queued generations would collide");
     for (;;) {
         std::vector<Request *> fresh;
         {
@@ -1520,20 +1562,25 @@ void plse_server_s::loop() {
         std::vector<std::pair<Request *, int>> done;
         for (Request *r : run) {
             int rc = PLSE_OK;
-            while (r->steps < r->queued) {
+            bool stopped = false;  // bound or iteration budget reached on the device
+            while (r->steps < r->queued && !stopped) {
                 const hipError_t q = hipEventQuery(r->S->ev[3 * (size_t)r->steps + 2]);
                 if (q == hipErrorNotReady) break;
                 if (q != hipSuccess) {
                     rc = hip_fail(q, "hipEventQuery");
                     break;
                 }
+                // this generation's copy of the flag landed before its end
+                // event (at most kAhead generations are enqueued beyond it)
+                stopped = __atomic_load_n(r->S->stop_host + r->steps % Session::kStopRing,
+                                          __ATOMIC_ACQUIRE) != 0;
                 r->steps += 1;
                 r->t_gen.push_back(now());
                 progressed = true;
             }
             const int fail_at = r->h->fail_at;
             const bool fault = fail_at && r->steps >= fail_at && r->steps < r->G;
-            if (rc || fault || r->steps >= r->G) {
+            if (rc || fault || stopped || r->steps >= r->G) {
                 // the request's stream drains before its workspace is released
                 const hipError_t q = hipStreamSynchronize(r->st);
                 if (!rc && q != hipSuccess) rc = hip_fail(q, "hipStreamSynchronize");

@@ -19,6 +19,8 @@ __global__ void ctl_reset_kernel(const ArgList L) {
         ctl->fstar = INT32_MAX;
         ctl->best_gen = 0;
         ctl->gens_run = 0;
+        ctl->stop_reason = 0;
+        ctl->iters = 0;
     }
 }
 
@@ -92,7 +94,15 @@ __global__ __launch_bounds__(1024) void best_kernel(const ArgList L) {
         gs.best_f = a.ctl->fstar;
         for (int q = 0; q < kCounters; ++q) gs.cnt[q] = s[q];
         a.ctl->gens_run = g;
-        if (a.stop_at_ub && a.nsq_minus_l - a.ctl->fstar == a.ub) a.ctl->stop = 1;
+        a.ctl->iters += s[0];
+        if (a.stop_at_ub && a.nsq_minus_l - a.ctl->fstar == a.ub) {
+            a.ctl->stop = 1;
+            a.ctl->stop_reason = 1;
+        } else if (a.max_iters > 0 && a.ctl->iters >= (uint64_t)a.max_iters) {
+            // iteration budget (Section 4.3), known at generation ends only
+            a.ctl->stop = 1;
+            a.ctl->stop_reason = 2;
+        }
     }
     __syncthreads();
     if (improved) {

@@ -68,6 +68,7 @@ struct BestArgs {
     const uint64_t *cnt;     // [p][kCounters]
     uint8_t *Sstar;          // [stride]
     int32_t p, stride, nsq_minus_l, ub, stop_at_ub;
+    int64_t max_iters;       // > 0: stop once ctl->iters reaches it
 };
 
 struct PackArgs {

@@ -50,6 +50,7 @@ struct Params {
     int64_t alpha_num, alpha_den;
     int64_t beta_num, beta_den;
     int64_t spacing;
+    int64_t max_iters;  // > 0: iteration budget of a run (Section 4.3), checked per generation
     int32_t stop_at_ub;
     int32_t hist_len;
     int32_t crossover;  // 0 AUX (Alg. 5), 1 UX (p_ij = 1/2), 2 none (Section 5.2)
@@ -60,11 +61,12 @@ struct Params {
 // Device control block of a solve (one per handle).
 struct Ctl {
     int32_t gen;          // current generation (1-based once started)
-    int32_t stop;         // set when the bound is reached with stop_at_ub
+    int32_t stop;         // set when the bound is reached with stop_at_ub, or the budget
     int32_t fstar;        // best f so far (INT32_MAX before generation 1)
     int32_t best_gen;
     int32_t gens_run;
-    int32_t pad[3];
+    int32_t stop_reason;  // 0 none, 1 bound reached, 2 iteration budget spent
+    uint64_t iters;       // tabu iterations of the whole population so far
 };
 
 // Per-generation record.

@@ -32,8 +32,14 @@ class PlseError(RuntimeError):
 
 class Stats(ctypes.Structure):
     _fields_ = [("generations_run", ctypes.c_int32), ("best_f", ctypes.c_int32),
-                ("best_generation", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("best_generation", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
                 ("totals", ctypes.c_uint64 * NCOUNTERS)]
+
+
+class Progress(ctypes.Structure):
+    _fields_ = [("generations_run", ctypes.c_int32), ("best_f", ctypes.c_int32),
+                ("best_generation", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
+                ("iterations", ctypes.c_uint64)]
 
 
 class Timing(ctypes.Structure):
@@ -52,6 +58,9 @@ def _lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        # torch's HIP runtime first: the library then binds to that same
+        # runtime (by soname) instead of loading a second one beside it
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64, u64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                 ctypes.c_size_t)
@@ -69,6 +78,7 @@ def _lib():
             "plse_solve_batch": [P, i32, i32, i32, P, P, P, P],
             "plse_step": [P, i32, P],
             "plse_end": [P, P, P, P],
+            "plse_peek": [P, P, P],
             "plse_last_timing": [P, P, P, P],
             "plse_last_stats": [P, P, P, P],
             "plse_stage_init": [P, i32, u64, P, P, P],
@@ -105,7 +115,7 @@ def exported_symbols():
     names = ["plse_create", "plse_info", "plse_sizes", "plse_row_stride", "plse_set_param", "plse_get_param",
              "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
              "plse_begin",
-             "plse_step", "plse_end", "plse_last_timing", "plse_last_stats",
+             "plse_step", "plse_end", "plse_peek", "plse_last_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
              "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux",
              "plse_server_create", "plse_server_submit", "plse_server_poll", "plse_server_status",
@@ -226,6 +236,14 @@ def plse_end(h, n: int, stream=None):
     return grid, filled.value
 
 
+def plse_peek(h, stream=None):
+    pr = Progress()
+    _check(_lib().plse_peek(h, _stream(stream), ctypes.byref(pr)), "plse_peek")
+    return dict(generations_run=pr.generations_run, best_f=pr.best_f,
+                best_generation=pr.best_generation, stop_reason=pr.stop_reason,
+                iterations=int(pr.iterations))
+
+
 def plse_last_timing(h):
     k = ctypes.c_int32()
     _check(_lib().plse_last_timing(h, ctypes.byref(k), None, None), "plse_last_timing")
@@ -243,7 +261,7 @@ def plse_last_stats(h):
     cnt = np.zeros((max(g, 1), NCOUNTERS), dtype=np.uint64)
     _check(_lib().plse_last_stats(h, ctypes.byref(st), _np(bf), _np(cnt)), "plse_last_stats")
     return dict(generations_run=g, best_f=st.best_f, best_generation=st.best_generation,
-                totals=np.array(st.totals[:], dtype=np.uint64), best_f_per_gen=bf[:g],
+                stop_reason=st.stop_reason, totals=np.array(st.totals[:], dtype=np.uint64), best_f_per_gen=bf[:g],
                 counters_per_gen=cnt[:g])
 
 
@@ -342,6 +360,9 @@ class Solver:
 
     def end(self, stream=None):
         return plse_end(self.h, self.n, stream)
+
+    def peek(self, stream=None):
+        return plse_peek(self.h, stream)
 
     def timing(self):
         return plse_last_timing(self.h)

@@ -80,9 +80,12 @@ def test_parameters_and_defaults():
         P.plse_set_param(h, "crossover", 2)
         P.plse_set_param(h, "matching", 1)
         assert P.plse_get_param(h, "crossover") == 2 and P.plse_get_param(h, "matching") == 1
+        assert P.plse_get_param(h, "max_iterations") == 0
+        P.plse_set_param(h, "max_iterations", 10 ** 11)
+        assert P.plse_get_param(h, "max_iterations") == 10 ** 11
         for key, val in (("nope", 1), ("slots_per_lane", 3), ("nn_history", 65), ("alpha_den", 0),
                          ("waves_per_block", 3), ("crossover", 3), ("matching", 2),
-                         ("variant", 2)):
+                         ("variant", 2), ("max_iterations", -1)):
             with pytest.raises(P.PlseError) as e:
                 P.plse_set_param(h, key, val)
             assert e.value.status == P.PLSE_E_PARAM
@@ -104,6 +107,9 @@ def test_workspace_planning_and_missing_workspace():
         assert e.value.status == P.PLSE_E_WORKSPACE
         with pytest.raises(P.PlseError) as e:
             P.plse_workspace_bytes(h, 1)
+        assert e.value.status == P.PLSE_E_ARG
+        with pytest.raises(P.PlseError) as e:  # no open session
+            P.plse_peek(h, stream=0)
         assert e.value.status == P.PLSE_E_ARG
         with pytest.raises(P.PlseError) as e:
             P.plse_workspace_bytes(h, 40000)

@@ -505,7 +505,7 @@ def test_run_stop_at_ub_and_determinism(oracle_mod):
     assert np.array_equal(r1["grid"], r2["grid"])
 
 
-# --- iteration budget (Section 4.2) --------------------------------------------------------
+# --- iteration budget (Section 4.3) --------------------------------------------------------
 def test_run_iteration_cap_on_a_hard_instance(oracle_mod):
     """On an instance whose bound is out of reach no individual ends a phase
     early, so each generation runs exactly p * depth iterations and a cap C
