@@ -662,7 +662,30 @@ __global__ __launch_bounds__(256) void match_kernel(const ArgList L) {
         // branch-free body, unrolled: several index and distance loads in
         // flight per lane
         uint64_t lb = ~0ull;
-        if (a.idx) {
+        if (a.idx && (a.ld & 7) == 0 && (a.m & 7) == 0) {
+            // the row in D order, eight entries per lane and 16-byte loads of
+            // D and of pos (which names the individual of each entry, -1 for
+            // candidates not selected)
+#pragma unroll 2
+            for (int x0 = lane * 8; x0 < a.m; x0 += 512) {
+                const u32x4 dq = gload4(row + x0);
+                const u32x4 pa = gload4(a.pos + x0);
+                const u32x4 pb = gload4(a.pos + x0 + 4);
+                const uint32_t dw[4] = {dq.x, dq.y, dq.z, dq.w};
+                const int32_t js[8] = {(int32_t)pa.x, (int32_t)pa.y, (int32_t)pa.z, (int32_t)pa.w,
+                                       (int32_t)pb.x, (int32_t)pb.y, (int32_t)pb.z, (int32_t)pb.w};
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int j = js[t];
+                    const uint32_t d = (dw[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+                    const int jc = j < 0 ? 0 : j;
+                    const bool ok = j >= 0 && j != i &&
+                                    (pass != 0 || !((excl[jc >> 5] >> (jc & 31)) & 1u));
+                    const uint64_t key = ok ? (((uint64_t)d << 32) | (uint32_t)j) : ~0ull;
+                    lb = key < lb ? key : lb;
+                }
+            }
+        } else if (a.idx) {
             // the row in D order (coalesced); pos names the individual of
             // each entry, -1 for candidates not selected
 #pragma unroll 8

@@ -326,6 +326,10 @@ def test_solve_variant_parity(torch_cuda, oracle_mod, name, p, G, depth, crossov
     ("greedy12_60", 32, 6, 1440, 0),
     ("greedy20_50", 48, 4, 2000, 0),
     ("planted10", 16, 8, 300, 1),
+    # populations not a multiple of 4: 2p % 8 != 0 takes the one-entry-per-lane
+    # scans of close lists and matching
+    ("greedy12_60", 30, 4, 1440, 0),
+    ("planted10", 18, 5, 600, 0),
 ])
 def test_solve_parity(torch_cuda, oracle_mod, name, p, G, depth, stop):
     g = _instances()[name]
