@@ -798,7 +798,8 @@ hipError_t launch_best(const ArgList &L, int count, hipStream_t stream) {
 }
 
 hipError_t launch_pack(const ArgList &L, int count, size_t max_threads, hipStream_t stream) {
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((max_threads + 255) / 256), count), dim3(256),
+    // at least one block: an instance without vertices packs nothing
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)std::max<size_t>(1, (max_threads + 255) / 256), count), dim3(256),
                        0, stream, L);
     return hipGetLastError();
 }

@@ -501,3 +501,39 @@ def test_server_capacity_and_fault_isolation(torch_cuda):
             np.testing.assert_array_equal(res[t]["grid"], ref[0])
     finally:
         srv.close()
+
+
+# --- degenerate and extreme instances ----------------------------------------------------
+def _edge_instances():
+    return {
+        "full10": gen.planted(10, 1.0, 0),                  # every cell prefilled: no vertex
+        "n1_empty": np.zeros((1, 1), dtype=np.int8),        # smallest order
+        "n2_empty": np.zeros((2, 2), dtype=np.int8),
+        "empty12": np.zeros((12, 12), dtype=np.int8),       # no prefilled cell: full domains
+        "greedy100_30": gen.random_greedy(100, 0.3, 4),     # largest order the survey measures
+        "planted127_60": gen.planted(127, 0.6, 1),          # largest order the boundary accepts
+        "greedy127_50": gen.random_greedy(127, 0.5, 1),
+    }
+
+
+@pytest.mark.parametrize("name,p,G,depth", [
+    ("full10", 4, 2, 100), ("n1_empty", 2, 2, 10), ("n2_empty", 4, 3, 40),
+    ("empty12", 16, 3, 1440), ("greedy100_30", 4, 2, 3000), ("planted127_60", 4, 2, 3000),
+    ("greedy127_50", 6, 2, 3000),
+])
+def test_solve_degenerate_and_extreme_orders(torch_cuda, oracle_mod, name, p, G, depth):
+    """Whole runs on an instance without vertices, the smallest orders, an
+    empty grid, and orders 100 and 127 (7 colour bit planes, 128 colours per
+    row of counts) equal the oracle's."""
+    g = _edge_instances()[name]
+    _say(f"solve edge {name} p={p} G={G} depth={depth}")
+    s = P.Solver(g, depth=depth)
+    grid, filled = s.solve(p, G, 31 + p)
+    st = s.stats()
+    I = oracle_mod.Instance(g)
+    r = I.run(I.params(depth=depth), p, G, 31 + p)
+    assert filled == r["filled"] and st["generations_run"] == r["gens"]
+    np.testing.assert_array_equal(grid, r["grid"])
+    np.testing.assert_array_equal(st["best_f_per_gen"], r["best_f"][:r["gens"]])
+    np.testing.assert_array_equal(st["counters_per_gen"], r["counters"][:r["gens"]])
+    assert filled <= s.ub and gen.is_partial_latin(grid)
