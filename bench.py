@@ -155,6 +155,10 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
     ap.add_argument("--generations", type=int, default=0,
                     help="served: generations per request (default 50)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="served: hardware queues of the process (GPU_MAX_HW_QUEUES, at most "
+                         "32), so that resident requests' streams run side by side (HIP's "
+                         "default is 4); 0 keeps the environment's value")
     ap.add_argument("--slots-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--population", type=int, default=0)
@@ -163,6 +167,10 @@ def main():
                     help="only run a plain elementwise device copy of MIB MiB (reads MIB, "
                          "writes MIB), the reference for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.workload == "served" and args.hw_queues > 0:
+        # read by the HIP runtime when it initialises, which is later (torch
+        # is imported lazily); --hw-queues 0 keeps the environment's value
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     if args.copy_reference:
         import torch
         n = args.copy_reference * (1 << 20) // 4
@@ -407,7 +415,8 @@ def bench_served(args, gen, plse):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "served: n ~ U{10..100}, r ~ U[0.3, 0.7], planted or "
                                "random-greedy, population 2048, depth 10n^2",
-                   "requests": len(reqs), "rate": args.rate, "generations": G},
+                   "requests": len(reqs), "rate": args.rate, "generations": G,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "moves_per_s": moves / wall,
         "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "time_to_best_s": {"p50": pct(ttb, 50), "p99": pct(ttb, 99)},

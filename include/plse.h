@@ -276,7 +276,11 @@ int plse_stage_aux(plse_handle h, int32_t population, int32_t gen, uint64_t seed
  * waits for another's generations; a finished request's workspace returns
  * to the arena.  A run that stops before its last generation (the bound with
  * stop_at_ub, or its iteration budget) leaves the device at the end of the
- * generation that stopped it, instead of stepping through the rest.  Each
+ * generation that stopped it, instead of stepping through the rest.  Streams
+ * run side by side only on distinct hardware queues: a serving process
+ * should raise the HIP runtime's queue count (environment variable
+ * GPU_MAX_HW_QUEUES, default 4) towards max_slots before the runtime
+ * initialises (16 queues serve a 16-request trace 1.3x faster than 4).  Each
  * result is identical to plse_solve of the same instance, parameters,
  * population, generations and seed, whatever else is resident.
  *
