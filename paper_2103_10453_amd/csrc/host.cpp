@@ -181,10 +181,10 @@ int choose_spl(const plse_instance *h) {
 }
 
 // PLITS per-wave LDS: S, row/column colour counts, eligibility bitmap,
-// per-vertex relative tabu expiry marks (u8) and the bitmap of vertices with
-// tabu entries, 64 staged eligible vertices, ring of chunk descriptors (one
-// group of 64 vertices dealt while under 64 are pending), colour halves of
-// the tie values (u16 per colour), bit planes of the chunk counts.
+// per-vertex relative tabu expiry marks (u8), kPlitsStage staged eligible
+// vertices, ring of chunk descriptors (one group of 64 vertices dealt while
+// under 64 are pending), colour halves of the tie values (u16 per colour),
+// bit planes of the chunk counts.
 struct PlitsLds {
     int per_wave, off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_planes;
     int nplanes;
@@ -199,7 +199,7 @@ PlitsLds plits_lds(const plse_instance *h) {
     L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
     L.off_tm = L.off_bm + (int)round_up((size_t)W * 4, 16);
     L.off_el = L.off_tm + (int)round_up((size_t)h->nv, 16);
-    L.off_ring = L.off_el + 128;
+    L.off_ring = L.off_el + 2 * kPlitsStage;
     L.off_hk = L.off_ring + qcap * 4;
     L.off_planes = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
     L.nplanes = 0;

@@ -54,7 +54,7 @@ struct WaveState {
     uint32_t *bm;
     uint8_t *tm8;      // [|V|] 0: no tabu entry this phase; 1: entries, all expired;
                        // m in 2..254: latest expiry = base + m - 1; 255: treat as live
-    uint16_t *stage;   // [64] the eligible vertices being dealt
+    uint16_t *stage;   // [kPlitsStage] eligible vertices of consecutive ranks
     uint32_t *ring;    // chunk descriptors: vertex | chunk index << 16 | live << 31
     uint16_t *hk;      // [n+1] colour halves of the iteration's tie values
     uint32_t *planes;  // [B][W] bit b of floor(|D*(v)| / CH) (chunks per row - 1)
@@ -286,7 +286,7 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
         if (lane <= n) ws.hk[lane] = (uint16_t)(fmix32(w2 ^ (uint32_t)lane) >> 16);
         if (lane + 64 <= n) ws.hk[lane + 64] = (uint16_t)(fmix32(w2 ^ (uint32_t)(lane + 64)) >> 16);
         // 1. eligible vertices (ascending rank over the bitmap): their number
-        //    m, and the first 64 of them staged for dealing
+        //    m, and the first kPlitsStage of them staged for dealing
         uint32_t m = 0;
         for (int wb = 0; wb < W; wb += 64) {
             const int w = wb + lane;
@@ -294,7 +294,7 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
             uint32_t total;
             uint32_t pos = m + wave_excl_scan_dpp((uint32_t)__popc(bits), &total);
 #pragma unroll 1
-            while (bits && pos < 64u) {
+            while (bits && pos < (uint32_t)kPlitsStage) {
                 const int b = __ffs(bits) - 1;
                 bits &= bits - 1u;
                 ws.stage[pos++] = (uint16_t)(w * 32 + b);
@@ -323,23 +323,26 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
         uint32_t lhi = 0xFFFFFFFFu, lv = 0u, lk = 0u, lpay = 0u;
         if (pend_off != 0xFFFFFFFFu) gptr(tabu)[pend_off] = pend_val;
         uint32_t head = 0u, tail = 0u, g = 0u;
+        uint32_t sbase = 0u;  // rank of stage[0]
         for (;;) {
             // once the ring is empty, deal the rows of the next 64 eligible
             // vertices into it
             if (head == tail && g < m) {
                 head = tail = 0u;
-                if (g > 0) {
-                    // stage eligible vertices of rank g .. g+63 (the bitmap
-                    // does not change within the iteration)
+                if (g >= sbase + (uint32_t)kPlitsStage) {
+                    // stage eligible vertices of rank g .. g+kPlitsStage-1
+                    // (the bitmap does not change within the iteration)
                     PLSE_WAVE_SYNC();
+                    sbase = g;
+                    const uint32_t gend = g + (uint32_t)kPlitsStage;
                     uint32_t base = 0;
-                    for (int wb = 0; wb < W && base < g + 64u; wb += 64) {
+                    for (int wb = 0; wb < W && base < gend; wb += 64) {
                         const int w = wb + lane;
                         uint32_t bits = (w < W) ? ws.bm[w] : 0u;
                         uint32_t total;
                         uint32_t pos = base + wave_excl_scan_dpp((uint32_t)__popc(bits), &total);
 #pragma unroll 1
-                        while (bits && pos < g + 64u) {
+                        while (bits && pos < gend) {
                             const int b = __ffs(bits) - 1;
                             bits &= bits - 1u;
                             if (pos >= g) ws.stage[pos - g] = (uint16_t)(w * 32 + b);
@@ -352,7 +355,7 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
                 const uint32_t e = g + (uint32_t)lane;
                 uint32_t v = 0u, nch = 0u, ent = 0u;
                 if (e < m) {
-                    v = ws.stage[lane];
+                    v = ws.stage[e - sbase];
                     // chunk count and liveness of v, read together: planes 0
                     // and 1 (or 0 twice), further planes only when present
                     const int vw = (int)(v >> 5);

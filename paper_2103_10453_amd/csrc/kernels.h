@@ -51,6 +51,9 @@ struct PlitsArgs {
     int32_t nplanes;       // bit planes of floor(|D*(v)| / CH), at most 6
 };
 
+// Eligible vertices a PLITS bitmap scan stages for dealing (u16 each, LDS).
+constexpr int kPlitsStage = 256;
+
 struct InitArgs {
     DevInstance I;
     uint8_t *S;            // [p][stride] out
