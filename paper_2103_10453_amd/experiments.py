@@ -26,6 +26,7 @@ from __future__ import annotations
 import argparse
 import dataclasses
 import json
+import sys
 import time
 
 import numpy as np
@@ -74,7 +75,7 @@ def trial_record(seed, filled, upper_bound, stats, plits_ms, rest_ms, seconds, s
 
 def run_trials(grid, runs: int = 5, population: int = 1024, generations: int = 1000,
                seed: int = 1, max_iterations: int = 0, time_limit_s: float | None = None,
-               chunk: int = 1, **params) -> list[Trial]:
+               chunk: int = 1, log=None, **params) -> list[Trial]:
     """`runs` independent runs on one instance (seeds seed, seed+1, ...).
 
     Each run stops after `generations`, or at the iteration budget, or, with
@@ -109,6 +110,9 @@ def run_trials(grid, runs: int = 5, population: int = 1024, generations: int = 1
         tp, tr = s.timing()
         out.append(trial_record(sd, filled, s.ub, st, tp, tr, secs,
                                 st["stop_reason"] or reason, grid=g))
+        if log:
+            log(f"  run seed {sd}: filled {filled} of bound {s.ub}, {st['generations_run']} "
+                f"generations, {secs:.1f} s")
     return out
 
 
@@ -134,24 +138,28 @@ def benchmark_instances(n: int, r: float, count: int, base: int = 5000) -> list[
 
 
 def table(grids, runs=5, population=1024, generations=1000, seed=1, max_iterations=0,
-          time_limit_s=None, **params) -> list[dict]:
-    """One row per instance: summarize() of `runs` trials."""
+          time_limit_s=None, log=None, **params) -> list[dict]:
+    """One row per instance: summarize() of `runs` trials.  `log`, if given,
+    receives a progress line after each instance."""
     rows = []
     for i, g in enumerate(grids):
         tr = run_trials(g, runs, population, generations, seed + 1000 * i, max_iterations,
-                        time_limit_s, **params)
+                        time_limit_s, log=log, **params)
         rows.append(dict(instance=i, n=int(np.asarray(g).shape[0]), **summarize(tr)))
+        if log:
+            log(f"population {population} instance {i}: f_best {rows[-1]['f_best']} "
+                f"f_avg {rows[-1]['f_avg']:.2f}")
     return rows
 
 
 def population_sweep(grids, populations, runs=5, generations=1000, seed=1, max_iterations=0,
-                     time_limit_s=None, **params) -> list[dict]:
+                     time_limit_s=None, log=None, **params) -> list[dict]:
     """Section 5.1: for each population size, the mean over instances of f_avg
     and f_best, the mean iterations and time to the best, and how many
     instances reach the best score found by any population size."""
     per_p = {}
     for p in populations:
-        per_p[p] = table(grids, runs, p, generations, seed, max_iterations, time_limit_s,
+        per_p[p] = table(grids, runs, p, generations, seed, max_iterations, time_limit_s, log,
                          **params)
     best = [max(per_p[p][i]["f_best"] for p in populations) for i in range(len(grids))]
     rows = []
@@ -207,14 +215,15 @@ def main(argv=None):
     if a.depth:
         params["depth"] = a.depth
     grids = benchmark_instances(a.n, a.r, a.instances)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
     if a.mode == "table":
         rows = table(grids, a.runs, a.population, a.generations, a.seed, int(a.max_iterations),
-                     a.time_limit, **params)
+                     a.time_limit, log, **params)
         text = _fmt_table(rows)
     else:
         pops = [int(x) for x in a.populations.split(",") if x]
         rows = population_sweep(grids, pops, a.runs, a.generations, a.seed,
-                                int(a.max_iterations), a.time_limit, **params)
+                                int(a.max_iterations), a.time_limit, log, **params)
         text = _fmt_sweep(rows)
     if a.json:
         for x in rows:
