@@ -278,7 +278,11 @@ def main():
                    "elig_per_gen": [int(x) for x in cnt[:, 4]],
                    "best_f_per_gen": [int(x) for x in st["best_f_per_gen"]],
                    "filled": filled, "upper_bound": s.ub,
-                   "plits_moves_per_s": moves_timed / (sum(t_plits) * 1e-3)},
+                   "plits_moves_per_s": moves_timed / (sum(t_plits) * 1e-3),
+                   # generation 1 (the first warm-up step): every search busy
+                   "first_generation": ({"moves": int(cnt[0, 1]), "plits_ms": float(ms_plits[0]),
+                                         "moves_per_s": float(cnt[0, 1]) / (float(ms_plits[0]) * 1e-3)}
+                                        if args.warmup >= 1 and gens >= 1 else None)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w["grid"], w["seed"], w["depth"])
