@@ -420,17 +420,35 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
     const int lane = tid;
     int na = 0, nr = 0;
     bool full = false;
+    // Loads run one block ahead of the decisions: while a block is decided,
+    // the next block's candidates, degrees and close lists (all kAdj entries,
+    // whatever the degree) and the keys of the block after it are in flight.
+    auto key_at = [&](int r) -> uint64_t {
+        return r < m ? (a.keys_in_lds ? K[r] : *gptr(a.keys_g + r)) : 0ull;
+    };
+    constexpr int kAdjV = kAdj / 8;  // 16-byte vectors per close list
+    u32x4 an[kAdjV];
+    int xn = (int)(key_at(lane) & 0xFFFFull);
+    int dn = lane < m ? *gptr(a.deg + xn) : 0;
+#pragma unroll
+    for (int q = 0; q < kAdjV; ++q)
+        an[q] = gload4(reinterpret_cast<const u32x4 *>(a.adj + (size_t)xn * kAdj) + q);
+    uint64_t krn = key_at(64 + lane);
     for (int base = 0; base < m && !full; base += 64) {
         const int r = base + lane;
         const bool valid = r < m;
-        const uint64_t kr = !valid ? 0ull : (a.keys_in_lds ? K[r] : *gptr(a.keys_g + r));
-        const int x = (int)(kr & 0xFFFFull);
-        const int d = valid ? *gptr(a.deg + x) : 0;
+        const int x = xn, d = dn;
         if (d > 0 && d <= kAdj) {
-            const u32x4 *src = reinterpret_cast<const u32x4 *>(a.adj + (size_t)x * kAdj);
             u32x4 *dst = reinterpret_cast<u32x4 *>(adjs + lane * kAdj);
-            for (int q = 0; q < (d + 7) / 8; ++q) dst[q] = gload4(src + q);
+#pragma unroll
+            for (int q = 0; q < kAdjV; ++q) dst[q] = an[q];
         }
+        xn = (int)(krn & 0xFFFFull);
+        dn = base + 64 + lane < m ? *gptr(a.deg + xn) : 0;
+#pragma unroll
+        for (int q = 0; q < kAdjV; ++q)
+            an[q] = gload4(reinterpret_cast<const u32x4 *>(a.adj + (size_t)xn * kAdj) + q);
+        krn = key_at(base + 128 + lane);
         PLSE_WAVE_SYNC();
         if (ballot(valid && d > kAdj) == 0) {
             // every close list is complete: decide the block in scan order on
@@ -439,9 +457,20 @@ __global__ __launch_bounds__(1024) void select_kernel(const ArgList L) {
             if (valid) inb[x] = (uint8_t)lane;
             PLSE_WAVE_SYNC();
             uint64_t mk = 0;
-            for (int q = 0; q < d; ++q) {
-                const uint32_t j = inb[adjs[lane * kAdj + q]];
-                if (j != 0xFFu && (int)j > lane) mk |= 1ull << j;
+            for (int q0 = 0; q0 < d; q0 += 8) {
+                // eight entries per 16-byte read, their lanes read together
+                const u32x4 e = reinterpret_cast<const u32x4 *>(adjs + lane * kAdj)[q0 >> 3];
+                const uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+                uint32_t js[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    // entries past d are not part of the list: clamp their index
+                    const uint32_t y = (ew[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+                    js[t] = inb[min(y, (uint32_t)(m - 1))];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (q0 + t < d && js[t] != 0xFFu && (int)js[t] > lane) mk |= 1ull << js[t];
             }
             PLSE_WAVE_SYNC();
             if (valid) inb[x] = 0xFF;
