@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0, choices=[0, 1],
                     help="0 MPMA, 1 Partial-MPMA (repair + PartialCol)")
     ap.add_argument("--instances", type=int, default=256, help="batch: number of instances")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch: pick each instance's launch shape by measurement first")
     ap.add_argument("--requests", type=int, default=16, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
     ap.add_argument("--generations", type=int, default=0,
@@ -302,6 +304,18 @@ def bench_batch(args, gen, plse):
     seeds = [w["seed"] for w in work]
     for s in solvers:
         s.ensure_workspace(p)
+    t_tune = None
+    if args.autotune:
+        # measured launch shapes per instance (results do not depend on them)
+        t0 = time.perf_counter()
+        for s, w in zip(solvers, work):
+            s.autotune(sample=p, depth=500, seed=w["seed"])
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t0
+    shapes = {}
+    for s in solvers:
+        k = f"{s.get_param('slots_per_lane')}x{s.get_param('waves_per_block')}"
+        shapes[k] = shapes.get(k, 0) + 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res_b = plse.Solver.solve_batch(solvers, p, G, seeds)
@@ -321,7 +335,9 @@ def bench_batch(args, gen, plse):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "batch: n ~ U{20..70}, r ~ U[0.3, 0.7], half planted, half "
                                "random-greedy, population 1024, depth 10n^2",
-                   "instances": len(work), "population": p},
+                   "instances": len(work), "population": p,
+                   "launch_shapes": "autotuned" if args.autotune else "cost model"},
+        "shapes": shapes, "autotune_seconds": t_tune,
         "one_instance_per_launch": {"value": moves_s / t_seq, "seconds": t_seq},
         "batched_seconds": t_batch, "speedup": t_seq / t_batch, "identical_results": same,
         "filled_total": int(sum(r[1] for r in res_b))}), flush=True)

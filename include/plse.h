@@ -118,6 +118,24 @@ int plse_row_stride(plse_handle h, int32_t *stride);
 int plse_set_param(plse_handle h, const char *key, int64_t value);
 int plse_get_param(plse_handle h, const char *key, int64_t *value);
 
+/*
+ * plse_autotune -- pick the tabu-search chunk size of this instance by
+ * measurement.  The initial population of `seed` (`sample` individuals, in
+ * the attached workspace, which must hold that population) runs one
+ * generation of phase-1 search of `depth` iterations with each candidate-
+ * positions-per-lane value that fits (2, 4, 8), each timed with HIP events on
+ * `stream` after one untimed launch; the fastest is stored as the handle's
+ * "slots_per_lane".  Waves per block keep the handle's setting (by default
+ * the occupancy rule, which also weighs the uneven search lengths of later
+ * generations that a short sample does not show).  The shape changes speed
+ * only: every result is the same under any shape; batches group instances
+ * by it.  out_ms (may be NULL) receives the 3 times in ms (slots 2, 4, 8), -1
+ * where a size does not fit.  Synchronises `stream`.  Errors: PLSE_E_ARG
+ * (sample < 2, depth < 1), PLSE_E_WORKSPACE, PLSE_E_BUSY, PLSE_E_HIP.
+ */
+int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, void *stream,
+                  float *out_ms);
+
 /* Bytes of device workspace a solve with this population needs. */
 int plse_workspace_bytes(plse_handle h, int32_t population, size_t *bytes);
 

@@ -1281,6 +1281,79 @@ int plse_stage_plits(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void 
     return PLSE_OK;
 }
 
+int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, void *stream,
+                  float *out_ms) {
+    if (!h || sample < 2 || depth < 1) return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok) return PLSE_E_BUSY;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    RC_TRY(stage_prepare(h, sample, s));
+    // the workspace's offspring, scratch and counter regions hold the sample
+    uint8_t *S_in = at<uint8_t>(h, h->L.S_off), *S_out = at<uint8_t>(h, h->L.S_tmp);
+    int32_t *f = at<int32_t>(h, h->L.f_tmp);
+    uint64_t *cnt = at<uint64_t>(h, h->L.cnt);
+    h->args.init = InitArgs{dev_instance(h), S_in, f, sample, next_pow2(std::max(4, h->nv)),
+                            (uint32_t)seed, (uint32_t)(seed >> 32)};
+    RC_TRY(upload_args(h, s));
+    HIP_TRY(launch_init(single(h, &ArgBlock::init), 1, sample,
+                        init_lds_bytes(h->args.init.I, h->args.init.pow2), s));
+    // phase-1 searches of `depth` iterations per chunk size; the waves per
+    // block stay with the handle's setting (or the occupancy rule), which
+    // also weighs the uneven search lengths of later generations
+    const Params saved = h->P;
+    const int spl0 = h->spl;
+    h->P.depth1 = depth;
+    h->P.depth2 = 0;
+    const int spls[3] = {2, 4, 8};
+    float ms[3] = {};
+    bool fits[3] = {};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = PLSE_OK;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && !rc) rc = hip_fail(e, what);
+    };
+    chk(hipEventCreate(&e0), "hipEventCreate");
+    chk(hipEventCreate(&e1), "hipEventCreate");
+    // round 0: one untimed launch (code loading, caches); round 1: every size
+    for (int round = 0; round < 2 && !rc; ++round) {
+        for (int i = 0; i < 3 && !rc; ++i) {
+            h->spl = spls[i];
+            const int per = plits_lds(h).per_wave, wpb = choose_wpb(h);
+            fits[i] = plits_fn(h->spl, h->P.variant != 0) != nullptr &&
+                      wpb * per <= max_lds_per_block();
+            if (!fits[i] || (round == 0 && i > 0)) continue;
+            h->args.plits = make_plits(h, sample, 1, seed, S_in, S_out, f, cnt, nullptr);
+            h->args.fill = FillArgs{at<uint32_t>(h, h->L.tabu), (size_t)sample * h->nv * h->ts};
+            const int up = upload_args(h, s);
+            if (up && !rc) rc = up;
+            if (rc) break;
+            chk(launch_fill_zero(single(h, &ArgBlock::fill), 1, s), "fill");
+            if (round == 1) chk(hipEventRecord(e0, s), "hipEventRecord");
+            chk(launch_plits(single(h, &ArgBlock::plits), 1, sample, per, h->spl, wpb,
+                             h->P.variant != 0, s),
+                "plits");
+            if (round == 1) {
+                chk(hipEventRecord(e1, s), "hipEventRecord");
+                chk(hipEventSynchronize(e1), "hipEventSynchronize");
+                chk(hipEventElapsedTime(&ms[i], e0, e1), "hipEventElapsedTime");
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    h->P = saved;
+    h->spl = spl0;
+    if (rc) return rc;
+    int best = -1;
+    for (int i = 0; i < 3; ++i) {
+        if (out_ms) out_ms[i] = fits[i] ? ms[i] : -1.0f;
+        if (fits[i] && (best < 0 || ms[i] < ms[best])) best = i;
+    }
+    if (best < 0) return PLSE_E_ARG;
+    h->spl = spls[best];
+    return PLSE_OK;
+}
+
 int plse_stage_distances(plse_handle h, int32_t m, void *stream, const uint8_t *S, int16_t *D) {
     if (!h || !S || !D || m < 1) return PLSE_E_ARG;
     BusyGuard guard(h);

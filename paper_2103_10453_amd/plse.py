@@ -79,6 +79,7 @@ def _lib():
             "plse_step": [P, i32, P],
             "plse_end": [P, P, P, P],
             "plse_peek": [P, P, P],
+            "plse_autotune": [P, i32, i32, u64, P, P],
             "plse_last_timing": [P, P, P, P],
             "plse_last_stats": [P, P, P, P],
             "plse_stage_init": [P, i32, u64, P, P, P],
@@ -115,7 +116,7 @@ def exported_symbols():
     names = ["plse_create", "plse_info", "plse_sizes", "plse_row_stride", "plse_set_param", "plse_get_param",
              "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
              "plse_begin",
-             "plse_step", "plse_end", "plse_peek", "plse_last_timing", "plse_last_stats",
+             "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_last_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
              "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux",
              "plse_server_create", "plse_server_submit", "plse_server_poll", "plse_server_status",
@@ -244,6 +245,13 @@ def plse_peek(h, stream=None):
                 iterations=int(pr.iterations))
 
 
+def plse_autotune(h, sample: int, depth: int, seed: int, stream=None):
+    ms = np.zeros(3, dtype=np.float32)
+    _check(_lib().plse_autotune(h, sample, depth, seed & ((1 << 64) - 1), _stream(stream),
+                                _np(ms)), "plse_autotune")
+    return ms
+
+
 def plse_last_timing(h):
     k = ctypes.c_int32()
     _check(_lib().plse_last_timing(h, ctypes.byref(k), None, None), "plse_last_timing")
@@ -363,6 +371,13 @@ class Solver:
 
     def peek(self, stream=None):
         return plse_peek(self.h, stream)
+
+    def autotune(self, sample: int = 4096, depth: int = 2000, seed: int = 1, stream=None):
+        """Measure the chunk sizes on `sample` individuals and keep the
+        fastest; returns the times (ms) for slots per lane 2, 4, 8 (-1: does
+        not fit)."""
+        self.ensure_workspace(sample)
+        return plse_autotune(self.h, sample, depth, seed, stream)
 
     def timing(self):
         return plse_last_timing(self.h)

@@ -111,6 +111,13 @@ def test_workspace_planning_and_missing_workspace():
         with pytest.raises(P.PlseError) as e:  # no open session
             P.plse_peek(h, stream=0)
         assert e.value.status == P.PLSE_E_ARG
+        for sample, depth in ((1, 100), (64, 0)):
+            with pytest.raises(P.PlseError) as e:
+                P.plse_autotune(h, sample, depth, 1, stream=0)
+            assert e.value.status == P.PLSE_E_ARG
+        with pytest.raises(P.PlseError) as e:  # workspace missing
+            P.plse_autotune(h, 64, 100, 1, stream=0)
+        assert e.value.status == P.PLSE_E_WORKSPACE
         with pytest.raises(P.PlseError) as e:
             P.plse_workspace_bytes(h, 40000)
         assert e.value.status == P.PLSE_E_ARG

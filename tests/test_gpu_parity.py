@@ -537,3 +537,31 @@ def test_solve_degenerate_and_extreme_orders(torch_cuda, oracle_mod, name, p, G,
     np.testing.assert_array_equal(st["best_f_per_gen"], r["best_f"][:r["gens"]])
     np.testing.assert_array_equal(st["counters_per_gen"], r["counters"][:r["gens"]])
     assert filled <= s.ub and gen.is_partial_latin(grid)
+
+
+# --- launch-shape autotuning ---------------------------------------------------------------
+def test_autotune_keeps_the_fastest_fitting_shape_and_the_results(torch_cuda, oracle_mod):
+    """plse_autotune times every chunk size that fits, keeps the fastest,
+    and a solve under the chosen size (alone and in a batch with other
+    autotuned instances) still equals the oracle."""
+    names = ["greedy12_60", "greedy20_50", "planted33_45"]
+    grids = [_instances()[k] for k in names]
+    solvers = []
+    for k, g in zip(names, grids):
+        _say(f"autotune {k}")
+        s = P.Solver(g, depth=600)
+        ms = s.autotune(sample=48, depth=300, seed=3)
+        fit = ms >= 0
+        assert fit.any() and np.all(ms[fit] > 0)
+        assert s.get_param("slots_per_lane") == (2, 4, 8)[int(np.argmin(np.where(fit, ms, np.inf)))]
+        solvers.append(s)
+    seeds = [71, 72, 73]
+    res = P.Solver.solve_batch(solvers, 24, 3, seeds)
+    for g, s, sd, (grid, filled) in zip(grids, solvers, seeds, res):
+        I = oracle_mod.Instance(g)
+        r = I.run(I.params(depth=600), 24, 3, sd)
+        assert filled == r["filled"]
+        np.testing.assert_array_equal(grid, r["grid"])
+        grid2, filled2 = s.solve(24, 3, sd)
+        assert filled2 == r["filled"]
+        np.testing.assert_array_equal(grid2, r["grid"])
