@@ -46,7 +46,25 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, OUT)
+    build_example()
     return OUT
+
+
+EXAMPLE_SRC = os.path.join(HERE, "examples", "plse_solve.c")
+EXAMPLE = os.path.join(HERE, "examples", "plse_solve")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def build_example() -> str:
+    """The plain-C command-line driver of the C ABI (gcc, no HIP device code)."""
+    include = os.path.join(os.path.dirname(HERE), "include")
+    tmp = EXAMPLE + ".tmp"
+    subprocess.check_call(["gcc", "-std=c99", "-O2", "-Wall", "-I", include,
+                           "-I", os.path.join(ROCM, "include"), EXAMPLE_SRC, "-o", tmp,
+                           "-L", HERE, "-lplse", "-L", os.path.join(ROCM, "lib"), "-lamdhip64",
+                           "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":

@@ -152,3 +152,25 @@ def test_server_argument_errors():
     assert L.plse_server_create(1 << 20, ctypes.c_void_p(4096), 0, None, ctypes.byref(srv)) == P.PLSE_E_ARG
     assert L.plse_server_submit(None, None, 8, 1, 1, None) == P.PLSE_E_ARG
     assert L.plse_server_destroy(None) == P.PLSE_E_ARG
+
+
+def _example():
+    import os
+    exe = os.path.join(os.path.dirname(P.library_path()), "examples", "plse_solve")
+    if not os.path.exists(exe):
+        pytest.skip("C example not built")
+    return exe
+
+
+def test_c_example_argument_errors_without_a_gpu():
+    """The plain-C driver compiles against include/plse.h as C99 and reports
+    argument and grid errors with the library's status codes (no device
+    call is reached)."""
+    import subprocess
+    exe = _example()
+    assert subprocess.run([exe], capture_output=True).returncode == P.PLSE_E_ARG
+    bad = "3\n1 1 0\n0 0 0\n0 0 0\n"  # symbol 1 twice in a row
+    r = subprocess.run([exe, "8", "2", "1"], input=bad.encode(), capture_output=True)
+    assert r.returncode == P.PLSE_E_GRID and b"plse_create" in r.stderr
+    r = subprocess.run([exe, "8", "2", "1"], input=b"3\n1 2\n", capture_output=True)
+    assert r.returncode == P.PLSE_E_ARG

@@ -565,3 +565,27 @@ def test_autotune_keeps_the_fastest_fitting_shape_and_the_results(torch_cuda, or
         grid2, filled2 = s.solve(24, 3, sd)
         assert filled2 == r["filled"]
         np.testing.assert_array_equal(grid2, r["grid"])
+
+
+def test_c_example_solves_like_the_oracle(torch_cuda, oracle_mod):
+    """The plain-C driver (its own process and HIP runtime, caller-owned
+    workspace from hipMalloc) returns the oracle's grid."""
+    import os
+    import subprocess
+    exe = os.path.join(os.path.dirname(P.library_path()), "examples", "plse_solve")
+    if not os.path.exists(exe):
+        pytest.skip("C example not built")
+    g = _instances()["greedy12_60"]
+    n = g.shape[0]
+    _say("C example greedy12_60 p=24 G=3")
+    text = f"{n}\n" + "\n".join(" ".join(str(int(v)) for v in row) for row in g) + "\n"
+    r = subprocess.run([exe, "24", "3", "17", "1440"], input=text.encode(), capture_output=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr.decode()
+    lines = r.stdout.decode().split("\n")
+    head = lines[0].split()
+    grid = np.array([[int(v) for v in lines[2 + i].split()] for i in range(n)], dtype=np.int8)
+    I = oracle_mod.Instance(g)
+    o = I.run(I.params(depth=1440), 24, 3, 17)
+    assert int(head[1]) == o["filled"] and int(head[3]) == I.ub and int(head[5]) == o["gens"]
+    np.testing.assert_array_equal(grid, o["grid"])
