@@ -204,6 +204,28 @@ typedef struct {
 int plse_peek(plse_handle h, void *stream, plse_progress *out);
 
 /*
+ * plse_checkpoint / plse_resume -- save the open session (plse_begin or
+ * plse_resume) at its generation boundary and continue it later, in this or
+ * another process, on a handle of the same grid and parameters.  The state
+ * of Alg. 2 between generations is the population P_t with f, the uids and
+ * partner histories of its members, the offspring waiting for the next
+ * search, S* and the per-generation statistics; all random draws are
+ * counter-based, so a resumed run is bit-identical to an uninterrupted one.
+ * plse_checkpoint waits for `stream` (every generation stepped so far), sets
+ * *bytes to the image size and, when buf is not NULL and capacity >= *bytes,
+ * writes the image to buf (host, caller-owned); the session stays open.
+ * plse_resume opens a session from an image (instead of plse_begin), with
+ * the handle's attached workspace (sized for `population`); continue with
+ * plse_step / plse_peek / plse_end.  plse_last_timing then covers the
+ * generations stepped since the resume.  Errors: PLSE_E_ARG (no open
+ * single-instance session, capacity too small, an image of another grid,
+ * parameters or population, or a damaged image), PLSE_E_WORKSPACE,
+ * PLSE_E_BUSY, PLSE_E_HIP.
+ */
+int plse_checkpoint(plse_handle h, void *stream, void *buf, size_t capacity, size_t *bytes);
+int plse_resume(plse_handle h, int32_t population, void *stream, const void *buf, size_t bytes);
+
+/*
  * plse_solve_batch -- plse_solve on `count` instances at once.
  *
  * Every generation of Alg. 2 runs for all instances together: one launch per

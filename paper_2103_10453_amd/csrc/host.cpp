@@ -489,7 +489,9 @@ struct PlitsGroup {
 struct Session {
     std::vector<plse_instance *> hs;  // launch order: longest estimated work first
     int p = 0;
-    int steps = 0;
+    int steps = 0;  // generations stepped in this session
+    int base = 0;   // generations run before it (a session resumed from a checkpoint)
+    uint64_t seed = 0;  // single-instance sessions
     std::vector<PlitsGroup> groups;  // largest estimated work first
     hipGraphExec_t ls = nullptr, rest = nullptr;  // ls only with a single group
     std::vector<hipEvent_t> ev;                   // 3 per generation
@@ -727,7 +729,7 @@ int session_begin(Session &S, const uint64_t *seeds, hipStream_t s) {
 }
 
 int session_step(Session &S, int generations, hipStream_t s) {
-    if (S.steps + generations > PLSE_MAX_GENERATIONS) return PLSE_E_ARG;
+    if (S.base + S.steps + generations > PLSE_MAX_GENERATIONS) return PLSE_E_ARG;
     while (S.ev.size() < 3 * (size_t)(S.steps + generations)) {
         hipEvent_t e = nullptr;
         HIP_TRY(hipEventCreate(&e));
@@ -766,7 +768,7 @@ int session_step(Session &S, int generations, hipStream_t s) {
 // Wait for the stream; per instance: statistics, timings and the best grid.
 int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &order,
                 int8_t *const *grids, int32_t *filled) {
-    const int G = std::max(S.steps, 1);
+    const int G = std::max(S.base + S.steps, 1);
     std::vector<Ctl> ctl(S.hs.size());
     std::vector<std::vector<GenStat>> gs(S.hs.size(), std::vector<GenStat>((size_t)G));
     std::vector<std::vector<uint8_t>> star(S.hs.size());
@@ -1111,6 +1113,7 @@ int plse_begin(plse_handle h, int32_t p, uint64_t seed, void *stream) {
     Session *S = new Session();
     S->hs = {h};
     S->p = p;
+    S->seed = seed;
     const int rc = session_begin(*S, &seed, reinterpret_cast<hipStream_t>(stream));
     if (rc) {
         delete S;
@@ -1154,6 +1157,134 @@ int plse_peek(plse_handle h, void *stream, plse_progress *out) {
     out->best_generation = c.best_gen;
     out->stop_reason = c.stop_reason;
     out->iterations = c.iters;
+    return PLSE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint image: header, then the device state at a generation boundary.
+struct CkptHeader {
+    uint32_t magic, version;
+    int32_t n, nv, stride, p;
+    uint64_t seed, ident;
+    int32_t gens_run, pad;
+};
+constexpr uint32_t kCkptMagic = 0x4B534C50u;  // "PLSK"
+
+// FNV-1a over the grid and every parameter that shapes a run.
+uint64_t run_ident(const plse_instance *h) {
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const uint8_t *b = static_cast<const uint8_t *>(p);
+        for (size_t i = 0; i < n; ++i) x = (x ^ b[i]) * 1099511628211ull;
+    };
+    mix(h->grid.data(), h->grid.size());
+    const Params &P = h->P;
+    const int64_t v[13] = {P.depth1, P.depth2, P.alpha_num, P.alpha_den, P.beta_num,
+                           P.beta_den, P.spacing, P.max_iters, P.stop_at_ub, P.hist_len,
+                           P.crossover, P.matching, P.variant};
+    mix(v, sizeof(v));
+    return x;
+}
+
+// The regions a checkpoint holds, in order: Ctl, the statistics of the
+// generations run, S*, P_t, f of P_t, uids, partner histories and their
+// counts, and the offspring waiting for the next generation's search.
+struct CkptPart {
+    size_t off, bytes;
+};
+std::vector<CkptPart> ckpt_parts(const plse_instance *h, int p, int gens) {
+    const Layout &L = h->L;
+    const size_t st = (size_t)h->stride, pp = (size_t)p;
+    return {{L.ctl, sizeof(Ctl)},          {L.stats, sizeof(GenStat) * (size_t)gens},
+            {L.Sstar, st},                 {L.S_all, pp * st},
+            {L.f_all, 4 * pp},             {L.uid, 8 * pp},
+            {L.hist, 8 * pp * kHist},      {L.hc, 4 * pp},
+            {L.S_off, pp * st}};
+}
+
+size_t ckpt_bytes(const std::vector<CkptPart> &parts) {
+    size_t b = sizeof(CkptHeader);
+    for (const CkptPart &c : parts) b += c.bytes;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plse_checkpoint(plse_handle h, void *stream, void *buf, size_t capacity, size_t *bytes) {
+    if (!h || !bytes) return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok) return PLSE_E_BUSY;
+    if (!h->in_session || !h->own || h->own->hs.size() != 1) return PLSE_E_ARG;
+    const Session &S = *h->own;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, at<Ctl>(h, h->L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const std::vector<CkptPart> parts = ckpt_parts(h, S.p, c.gens_run);
+    *bytes = ckpt_bytes(parts);
+    if (!buf) return PLSE_OK;
+    if (capacity < *bytes) return PLSE_E_ARG;
+    CkptHeader hd{kCkptMagic, 1u, h->n, h->nv, h->stride, S.p, S.seed, run_ident(h),
+                  c.gens_run, 0};
+    uint8_t *out = static_cast<uint8_t *>(buf);
+    std::memcpy(out, &hd, sizeof(hd));
+    size_t o = sizeof(hd);
+    for (const CkptPart &q : parts) {
+        if (q.bytes)
+            HIP_TRY(hipMemcpyAsync(out + o, h->ws + q.off, q.bytes, hipMemcpyDeviceToHost, s));
+        o += q.bytes;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return PLSE_OK;
+}
+
+int plse_resume(plse_handle h, int32_t p, void *stream, const void *buf, size_t bytes) {
+    if (!h || !buf || bytes < sizeof(CkptHeader)) return PLSE_E_ARG;
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (hd.magic != kCkptMagic || hd.version != 1u || hd.n != h->n || hd.nv != h->nv ||
+        hd.stride != h->stride || hd.p != p || hd.ident != run_ident(h) || hd.gens_run < 0 ||
+        hd.gens_run > PLSE_MAX_GENERATIONS)
+        return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok) return PLSE_E_BUSY;
+    RC_TRY(check_ws(h, p));
+    const std::vector<CkptPart> parts = ckpt_parts(h, p, hd.gens_run);
+    if (bytes != ckpt_bytes(parts)) return PLSE_E_ARG;
+    drop_session(h);
+    Session *S = new Session();
+    S->hs = {h};
+    S->p = p;
+    S->seed = hd.seed;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // a fresh session of the same seed, then its state replaced by the image
+    int rc = session_begin(*S, &hd.seed, s);
+    const uint8_t *in = static_cast<const uint8_t *>(buf);
+    size_t o = sizeof(hd);
+    for (const CkptPart &q : parts) {
+        if (!rc && q.bytes) {
+            const hipError_t e =
+                hipMemcpyAsync(h->ws + q.off, in + o, q.bytes, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) rc = hip_fail(e, "plse_resume");
+        }
+        o += q.bytes;
+    }
+    if (!rc) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "plse_resume");
+    }
+    if (rc) {
+        delete S;
+        return rc;
+    }
+    S->base = hd.gens_run;
+    h->own = S;
+    h->in_session = true;
     return PLSE_OK;
 }
 

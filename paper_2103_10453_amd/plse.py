@@ -80,6 +80,8 @@ def _lib():
             "plse_end": [P, P, P, P],
             "plse_peek": [P, P, P],
             "plse_autotune": [P, i32, i32, u64, P, P],
+            "plse_checkpoint": [P, P, P, sz, P],
+            "plse_resume": [P, i32, P, P, sz],
             "plse_last_timing": [P, P, P, P],
             "plse_last_stats": [P, P, P, P],
             "plse_stage_init": [P, i32, u64, P, P, P],
@@ -116,7 +118,7 @@ def exported_symbols():
     names = ["plse_create", "plse_info", "plse_sizes", "plse_row_stride", "plse_set_param", "plse_get_param",
              "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
              "plse_begin",
-             "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_last_timing", "plse_last_stats",
+             "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_checkpoint", "plse_resume", "plse_last_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
              "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux",
              "plse_server_create", "plse_server_submit", "plse_server_poll", "plse_server_status",
@@ -252,6 +254,21 @@ def plse_autotune(h, sample: int, depth: int, seed: int, stream=None):
     return ms
 
 
+def plse_checkpoint(h, stream=None) -> np.ndarray:
+    n = ctypes.c_size_t()
+    _check(_lib().plse_checkpoint(h, _stream(stream), None, 0, ctypes.byref(n)), "plse_checkpoint")
+    buf = np.zeros(n.value, dtype=np.uint8)
+    _check(_lib().plse_checkpoint(h, _stream(stream), _np(buf), buf.nbytes, ctypes.byref(n)),
+           "plse_checkpoint")
+    return buf
+
+
+def plse_resume(h, population: int, image, stream=None):
+    image = np.ascontiguousarray(np.asarray(image, dtype=np.uint8))
+    _check(_lib().plse_resume(h, population, _stream(stream), _np(image), image.nbytes),
+           "plse_resume")
+
+
 def plse_last_timing(h):
     k = ctypes.c_int32()
     _check(_lib().plse_last_timing(h, ctypes.byref(k), None, None), "plse_last_timing")
@@ -371,6 +388,15 @@ class Solver:
 
     def peek(self, stream=None):
         return plse_peek(self.h, stream)
+
+    def checkpoint(self, stream=None):
+        """Image (uint8 array) of the open session at its generation boundary."""
+        return plse_checkpoint(self.h, stream)
+
+    def resume(self, population: int, image, stream=None):
+        """Open a session from a checkpoint image (instead of begin)."""
+        self.ensure_workspace(population)
+        plse_resume(self.h, population, image, stream)
 
     def autotune(self, sample: int = 4096, depth: int = 2000, seed: int = 1, stream=None):
         """Measure the chunk sizes on `sample` individuals and keep the

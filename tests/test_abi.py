@@ -118,6 +118,13 @@ def test_workspace_planning_and_missing_workspace():
         with pytest.raises(P.PlseError) as e:  # workspace missing
             P.plse_autotune(h, 64, 100, 1, stream=0)
         assert e.value.status == P.PLSE_E_WORKSPACE
+        with pytest.raises(P.PlseError) as e:  # no open session to checkpoint
+            P.plse_checkpoint(h, stream=0)
+        assert e.value.status == P.PLSE_E_ARG
+        for image in (np.zeros(8, dtype=np.uint8), np.arange(4096, dtype=np.uint32).view(np.uint8)):
+            with pytest.raises(P.PlseError) as e:  # not a checkpoint image
+                P.plse_resume(h, 64, image, stream=0)
+            assert e.value.status == P.PLSE_E_ARG
         with pytest.raises(P.PlseError) as e:
             P.plse_workspace_bytes(h, 40000)
         assert e.value.status == P.PLSE_E_ARG

@@ -171,3 +171,46 @@ def test_served_runs_that_stop_early_leave_at_their_stop(torch_cuda):
             np.testing.assert_array_equal(r["grid"], want[i][0])
     finally:
         srv.close()
+
+
+def test_checkpoint_resume_equals_uninterrupted_run(torch_cuda, oracle_mod):
+    """A session checkpointed after 2 generations and resumed on a fresh
+    handle (its own workspace) for 3 more equals the uninterrupted 5-generation
+    run and the oracle's, statistics included; a second checkpoint of the
+    resumed session continues the same way; an image of other parameters or
+    another population is refused."""
+    g = HARD["grid"]()
+    p, depth, seed = 24, 1440, 99
+    I = oracle_mod.Instance(g)
+    full = I.run(I.params(depth=depth), p, 5, seed)
+    _say("checkpoint after 2 generations, resume for 3")
+    s1 = P.Solver(g, depth=depth)
+    s1.begin(p, seed)
+    s1.step(2)
+    img = s1.checkpoint()
+    s1.step(1)
+    img3 = s1.checkpoint()
+    s1.end()
+    s2 = P.Solver(g, depth=depth)
+    s2.resume(p, img)
+    s2.step(3)
+    grid, filled = s2.end()
+    st = s2.stats()
+    assert filled == full["filled"] and st["generations_run"] == full["gens"] == 5
+    np.testing.assert_array_equal(grid, full["grid"])
+    np.testing.assert_array_equal(st["best_f_per_gen"], full["best_f"])
+    np.testing.assert_array_equal(st["counters_per_gen"], full["counters"])
+    assert len(s2.timing()[0]) == 3
+    _say("resume from generation 3 on the first handle")
+    s1.resume(p, img3)
+    s1.step(2)
+    grid3, filled3 = s1.end()
+    assert filled3 == full["filled"]
+    np.testing.assert_array_equal(grid3, full["grid"])
+    other = P.Solver(g, depth=depth + 8)
+    with pytest.raises(P.PlseError) as e:
+        other.resume(p, img)
+    assert e.value.status == P.PLSE_E_ARG
+    with pytest.raises(P.PlseError) as e:
+        s2.resume(p + 2, img)
+    assert e.value.status == P.PLSE_E_ARG
