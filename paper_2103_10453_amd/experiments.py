@@ -73,9 +73,32 @@ def trial_record(seed, filled, upper_bound, stats, plits_ms, rest_ms, seconds, s
                  stop_reason=int(stop_reason), grid=grid)
 
 
+def generation_records(stats, plits_ms, rest_ms, n_cells: int, impossible: int) -> list[dict]:
+    """One record per generation of a run: generation, best f, score (filled
+    cells of S* = n^2 - l - f), the eight counters and the generation's GPU
+    times (tabu search, rest of the generation) in ms.  Timings cover the
+    generations stepped in the session; earlier ones (before a resume) get
+    None."""
+    cnt = np.asarray(stats["counters_per_gen"], dtype=np.uint64).reshape(-1, P.NCOUNTERS)
+    names = ["iterations", "moves", "idle", "candidates", "eligible", "updates", "snapshots",
+             "repairs"]
+    g = int(stats["generations_run"])
+    off = g - len(plits_ms)
+    out = []
+    for k in range(g):
+        f = int(stats["best_f_per_gen"][k])
+        rec = dict(generation=k + 1, best_f=f, score=n_cells - impossible - f)
+        rec.update({nm: int(cnt[k, q]) for q, nm in enumerate(names)})
+        t = k - off
+        rec["plits_ms"] = float(plits_ms[t]) if 0 <= t < len(plits_ms) else None
+        rec["rest_ms"] = float(rest_ms[t]) if 0 <= t < len(rest_ms) else None
+        out.append(rec)
+    return out
+
+
 def run_trials(grid, runs: int = 5, population: int = 1024, generations: int = 1000,
                seed: int = 1, max_iterations: int = 0, time_limit_s: float | None = None,
-               chunk: int = 1, log=None, **params) -> list[Trial]:
+               chunk: int = 1, log=None, gen_log=None, **params) -> list[Trial]:
     """`runs` independent runs on one instance (seeds seed, seed+1, ...).
 
     Each run stops after `generations`, or at the iteration budget, or, with
@@ -113,6 +136,9 @@ def run_trials(grid, runs: int = 5, population: int = 1024, generations: int = 1
         if log:
             log(f"  run seed {sd}: filled {filled} of bound {s.ub}, {st['generations_run']} "
                 f"generations, {secs:.1f} s")
+        if gen_log:
+            for rec in generation_records(st, tp, tr, s.n * s.n, s.l):
+                gen_log(dict(seed=sd, upper_bound=s.ub, **rec))
     return out
 
 
@@ -138,13 +164,16 @@ def benchmark_instances(n: int, r: float, count: int, base: int = 5000) -> list[
 
 
 def table(grids, runs=5, population=1024, generations=1000, seed=1, max_iterations=0,
-          time_limit_s=None, log=None, **params) -> list[dict]:
+          time_limit_s=None, log=None, gen_log=None, **params) -> list[dict]:
     """One row per instance: summarize() of `runs` trials.  `log`, if given,
     receives a progress line after each instance."""
     rows = []
     for i, g in enumerate(grids):
         tr = run_trials(g, runs, population, generations, seed + 1000 * i, max_iterations,
-                        time_limit_s, log=log, **params)
+                        time_limit_s, log=log,
+                        gen_log=(lambda r, i=i: gen_log(dict(instance=i, population=population,
+                                                             **r))) if gen_log else None,
+                        **params)
         rows.append(dict(instance=i, n=int(np.asarray(g).shape[0]), **summarize(tr)))
         if log:
             log(f"population {population} instance {i}: f_best {rows[-1]['f_best']} "
@@ -210,6 +239,8 @@ def main(argv=None):
     ap.add_argument("--variant", type=int, default=0, help="1: Partial-MPMA")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--json", action="store_true", help="one JSON line per row")
+    ap.add_argument("--log", default=None, metavar="FILE",
+                    help="table: append one JSON line per generation of every run to FILE")
     a = ap.parse_args(argv)
     params = dict(variant=a.variant)
     if a.depth:
@@ -217,8 +248,12 @@ def main(argv=None):
     grids = benchmark_instances(a.n, a.r, a.instances)
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
     if a.mode == "table":
+        fh = open(a.log, "a") if a.log else None
+        gen_log = (lambda r: (fh.write(json.dumps(r) + "\n"), fh.flush())) if fh else None
         rows = table(grids, a.runs, a.population, a.generations, a.seed, int(a.max_iterations),
-                     a.time_limit, log, **params)
+                     a.time_limit, log, gen_log, **params)
+        if fh:
+            fh.close()
         text = _fmt_table(rows)
     else:
         pops = [int(x) for x in a.populations.split(",") if x]

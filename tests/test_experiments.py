@@ -66,3 +66,15 @@ def test_benchmark_instances_shape_and_seeds():
         assert gen.is_partial_latin(x)
         assert x.shape == (20, 20)
     assert not np.array_equal(a[0], a[1])
+
+
+def test_generation_records():
+    st = _stats([10, 20, 30], 2)
+    st["best_f_per_gen"] = np.array([5, 3, 3], dtype=np.int32)
+    st["counters_per_gen"][:, 1] = [9, 18, 27]
+    recs = E.generation_records(st, [1.0, 2.0], [0.5, 0.25], 100, 2)  # resumed: 2 timed
+    assert [r["generation"] for r in recs] == [1, 2, 3]
+    assert [r["score"] for r in recs] == [93, 95, 95]
+    assert [r["iterations"] for r in recs] == [10, 20, 30]
+    assert [r["moves"] for r in recs] == [9, 18, 27]
+    assert recs[0]["plits_ms"] is None and recs[1]["plits_ms"] == 1.0 and recs[2]["rest_ms"] == 0.25

@@ -101,9 +101,16 @@ def test_trials_and_summary_equal_independent_solves(torch_cuda, oracle_mod):
     g = gen.random_greedy(12, 0.6, 5)
     I = oracle_mod.Instance(g)
     _say("experiments.run_trials runs=3")
-    tr = E.run_trials(g, runs=3, population=16, generations=4, seed=500, depth=1440)
+    recs = []
+    tr = E.run_trials(g, runs=3, population=16, generations=4, seed=500, depth=1440,
+                      gen_log=recs.append)
+    assert len(recs) == 12
     for t in tr:
         r = I.run(I.params(depth=1440), 16, 4, t.seed)
+        mine = [x for x in recs if x["seed"] == t.seed]
+        assert [x["best_f"] for x in mine] == [int(v) for v in r["best_f"]]
+        assert [x["moves"] for x in mine] == [int(v) for v in r["counters"][:, 1]]
+        assert all(x["plits_ms"] > 0 for x in mine)
         assert t.filled == r["filled"] and t.generations == r["gens"] == 4
         np.testing.assert_array_equal(t.grid, r["grid"])
         bg = 1 + int(np.argmax(r["best_f"] == r["best_f"][-1]))
