@@ -30,7 +30,8 @@ enum {
     PLSE_PENDING = 6,      /* server: request not finished yet                  */
     PLSE_E_PARAM = 7,      /* unknown parameter key or value out of range       */
     PLSE_E_CAPACITY = 8,   /* server: request cannot ever fit the budget        */
-    PLSE_E_FAULT = 9       /* server: request ended by the fault-injection hook */
+    PLSE_E_FAULT = 9,      /* server: request ended by the fault-injection hook */
+    PLSE_E_CANCELLED = 10  /* server: request cancelled (plse_server_cancel)    */
 };
 
 typedef struct plse_instance *plse_handle;
@@ -358,6 +359,11 @@ int plse_server_submit(plse_server s, plse_handle h, int32_t population, int32_t
 int plse_server_poll(plse_server s, uint64_t ticket, int8_t *best_grid, int32_t *filled,
                      plse_timing *timing);
 /* Requests waiting, resident, and finished but not yet polled. */
+/* plse_server_cancel: a waiting request is dropped (poll: PLSE_E_CANCELLED, no
+ * grid); a resident one stops at the end of its current generation and its
+ * poll returns PLSE_E_CANCELLED with the best grid found so far (filled and
+ * timing set).  PLSE_E_ARG for an unknown or already finished ticket. */
+int plse_server_cancel(plse_server s, uint64_t ticket);
 int plse_server_status(plse_server s, int32_t *waiting, int32_t *resident, int32_t *finished);
 int plse_server_destroy(plse_server s);
 

@@ -1370,6 +1370,7 @@ const char *plse_strerror(int status) {
         case PLSE_E_PARAM: return "unknown parameter or value out of range";
         case PLSE_E_CAPACITY: return "request exceeds the server capacity";
         case PLSE_E_FAULT: return "request ended by the fault-injection hook";
+        case PLSE_E_CANCELLED: return "request cancelled";
         default: return "unknown status";
     }
 }
@@ -1579,6 +1580,7 @@ struct Request {
     std::vector<int8_t> grid;
     int filled = 0, best_gen = 0;
     uint64_t moves = 0;
+    std::atomic<bool> cancel{false};  // plse_server_cancel on a resident request
 };
 
 // Results of one finished request (the stream is idle).
@@ -1641,6 +1643,7 @@ struct plse_server_s {
     std::vector<Request *> resident;
     std::map<uint64_t, Request *> finished;
     std::set<uint64_t> live;  // submitted and not yet finished (waiting, admitting, resident)
+    std::set<uint64_t> cancelled;  // cancel requests for tickets being admitted
     std::map<size_t, size_t> free_blocks;  // offset -> bytes
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -1682,6 +1685,7 @@ struct plse_server_s {
     }
 
     void finish(Request *r, int status) {
+        cancelled.erase(r->ticket);
         r->status = status;
         r->t_done = now();
         r->h->ws = nullptr;
@@ -1755,6 +1759,7 @@ void plse_server_s::loop() {
                 finish(r, e);
             } else {
                 r->t_admit = now();
+                if (cancelled.erase(r->ticket)) r->cancel.store(true);
                 resident.push_back(r);
             }
         }
@@ -1784,12 +1789,15 @@ void plse_server_s::loop() {
             }
             const int fail_at = r->h->fail_at;
             const bool fault = fail_at && r->steps >= fail_at && r->steps < r->G;
-            if (rc || fault || stopped || r->steps >= r->G) {
+            const bool cancel = r->cancel.load() && r->steps < r->G && !stopped;
+            if (rc || fault || stopped || cancel || r->steps >= r->G) {
                 // the request's stream drains before its workspace is released
                 const hipError_t q = hipStreamSynchronize(r->st);
                 if (!rc && q != hipSuccess) rc = hip_fail(q, "hipStreamSynchronize");
                 if (!rc && fault) rc = PLSE_E_FAULT;
                 if (!rc) rc = collect(*r, r->st);
+                // cancelled: the best grid so far is returned with its status
+                if (!rc && cancel) rc = PLSE_E_CANCELLED;
                 done.emplace_back(r, rc);
                 progressed = true;
                 continue;
@@ -1906,6 +1914,33 @@ int plse_server_poll(plse_server s, uint64_t ticket, int8_t *best_grid, int32_t 
     const int st = r->status;
     delete r;
     return st;
+}
+
+int plse_server_cancel(plse_server s, uint64_t ticket) {
+    if (!s) return PLSE_E_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->live.count(ticket)) return PLSE_E_ARG;  // unknown, or already finished
+    for (auto it = s->waiting.begin(); it != s->waiting.end(); ++it) {
+        Request *r = *it;
+        if (r->ticket != ticket) continue;
+        // never admitted: no workspace, no stream, no result
+        s->waiting.erase(it);
+        r->status = PLSE_E_CANCELLED;
+        r->t_done = s->now();
+        r->h->in_session = false;
+        s->live.erase(ticket);
+        s->finished[ticket] = r;
+        return PLSE_OK;
+    }
+    // admitted: the worker stops it at its next generation end; being
+    // admitted: the cancellation is applied when it becomes resident
+    for (Request *r : s->resident)
+        if (r->ticket == ticket) {
+            r->cancel.store(true);
+            return PLSE_OK;
+        }
+    s->cancelled.insert(ticket);
+    return PLSE_OK;
 }
 
 int plse_server_status(plse_server s, int32_t *waiting, int32_t *resident, int32_t *finished) {

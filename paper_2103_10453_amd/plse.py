@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libplse.so")
 
 PLSE_OK, PLSE_E_ARG, PLSE_E_GRID, PLSE_E_WORKSPACE, PLSE_E_HIP, PLSE_E_BUSY, PLSE_PENDING, \
-    PLSE_E_PARAM, PLSE_E_CAPACITY, PLSE_E_FAULT = range(10)
+    PLSE_E_PARAM, PLSE_E_CAPACITY, PLSE_E_FAULT, PLSE_E_CANCELLED = range(11)
 NCOUNTERS = 8
 COUNTER_NAMES = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs"]
 HIST = 64
@@ -94,6 +94,7 @@ def _lib():
             "plse_server_submit": [P, P, i32, i32, u64, P],
             "plse_server_poll": [P, u64, P, P, P],
             "plse_server_status": [P, P, P, P],
+            "plse_server_cancel": [P, u64],
             "plse_server_destroy": [P],
         }
         for name, args in sigs.items():
@@ -122,6 +123,7 @@ def exported_symbols():
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
              "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux",
              "plse_server_create", "plse_server_submit", "plse_server_poll", "plse_server_status",
+             "plse_server_cancel",
              "plse_server_destroy"]
     return [n for n in names if hasattr(L, n)]
 
@@ -503,6 +505,10 @@ def plse_server_poll(srv, ticket: int, n: int):
     return st, grid, filled.value, t
 
 
+def plse_server_cancel(srv, ticket: int):
+    _check(_lib().plse_server_cancel(srv, ticket), "plse_server_cancel")
+
+
 def plse_server_status(srv):
     a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(_lib().plse_server_status(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
@@ -543,6 +549,9 @@ class Server:
 
     def status(self):
         return plse_server_status(self.srv)
+
+    def cancel(self, ticket: int):
+        plse_server_cancel(self.srv, ticket)
 
     def close(self):
         if self.srv:

@@ -221,3 +221,41 @@ def test_checkpoint_resume_equals_uninterrupted_run(torch_cuda, oracle_mod):
     with pytest.raises(P.PlseError) as e:
         s2.resume(p + 2, img)
     assert e.value.status == P.PLSE_E_ARG
+
+
+def test_server_cancel_waiting_and_resident_requests(torch_cuda):
+    """A cancelled waiting request ends without running; a cancelled resident
+    one stops at a generation end and returns a legal best grid so far; the
+    server keeps serving others, with results equal to plse_solve."""
+    import time
+    _say("serving: cancellation")
+    small = gen.planted(10, 0.4, 0)
+    want = P.Solver(small, depth=300).solve(16, 5, 2)
+    srv = P.Server(1 << 30, max_slots=1)
+    try:
+        long = P.Solver(gen.random_greedy(30, 0.5, 3), depth=9000)
+        t1 = srv.submit(long, 64, 500, 1)
+        t2 = srv.submit(P.Solver(small, depth=300), 16, 5, 2)
+        t0 = time.time()
+        while srv.status()[1] < 1:
+            assert time.time() - t0 < 60
+            time.sleep(0.01)
+        time.sleep(0.5)
+        srv.cancel(t2)
+        srv.cancel(t1)
+        res = _wait(srv, [t1, t2])
+        assert res[t2]["status"] == P.PLSE_E_CANCELLED and res[t2]["generations"] == 0
+        r1 = res[t1]
+        assert r1["status"] == P.PLSE_E_CANCELLED
+        assert 1 <= r1["generations"] < 500
+        assert gen.is_partial_latin(r1["grid"]) and 0 < r1["filled"] <= long.ub
+        for t in (t1, 12345):
+            with pytest.raises(P.PlseError) as e:
+                srv.cancel(t)
+            assert e.value.status == P.PLSE_E_ARG
+        t3 = srv.submit(P.Solver(small, depth=300), 16, 5, 2)
+        r3 = _wait(srv, [t3])[t3]
+        assert r3["status"] == P.PLSE_OK and r3["filled"] == want[1]
+        np.testing.assert_array_equal(r3["grid"], want[0])
+    finally:
+        srv.close()
