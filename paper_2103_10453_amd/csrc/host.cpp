@@ -1446,25 +1446,25 @@ int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, v
     };
     chk(hipEventCreate(&e0), "hipEventCreate");
     chk(hipEventCreate(&e1), "hipEventCreate");
-    // round 0: one untimed launch (code loading, caches); round 1: every size
-    for (int round = 0; round < 2 && !rc; ++round) {
+    // pass 0: one untimed launch (code loading, caches); pass 1: every size
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
         for (int i = 0; i < 3 && !rc; ++i) {
             h->spl = spls[i];
             const int per = plits_lds(h).per_wave, wpb = choose_wpb(h);
             fits[i] = plits_fn(h->spl, h->P.variant != 0) != nullptr &&
                       wpb * per <= max_lds_per_block();
-            if (!fits[i] || (round == 0 && i > 0)) continue;
+            if (!fits[i] || (pass == 0 && i > 0)) continue;
             h->args.plits = make_plits(h, sample, 1, seed, S_in, S_out, f, cnt, nullptr);
             h->args.fill = FillArgs{at<uint32_t>(h, h->L.tabu), (size_t)sample * h->nv * h->ts};
             const int up = upload_args(h, s);
             if (up && !rc) rc = up;
             if (rc) break;
             chk(launch_fill_zero(single(h, &ArgBlock::fill), 1, s), "fill");
-            if (round == 1) chk(hipEventRecord(e0, s), "hipEventRecord");
+            if (pass == 1) chk(hipEventRecord(e0, s), "hipEventRecord");
             chk(launch_plits(single(h, &ArgBlock::plits), 1, sample, per, h->spl, wpb,
                              h->P.variant != 0, s),
                 "plits");
-            if (round == 1) {
+            if (pass == 1) {
                 chk(hipEventRecord(e1, s), "hipEventRecord");
                 chk(hipEventSynchronize(e1), "hipEventSynchronize");
                 chk(hipEventElapsedTime(&ms[i], e0, e1), "hipEventElapsedTime");

@@ -510,7 +510,7 @@ def _edge_instances():
         "n1_empty": np.zeros((1, 1), dtype=np.int8),        # smallest order
         "n2_empty": np.zeros((2, 2), dtype=np.int8),
         "empty12": np.zeros((12, 12), dtype=np.int8),       # no prefilled cell: full domains
-        "greedy100_30": gen.random_greedy(100, 0.3, 4),     # largest order the survey measures
+        "greedy100_30": gen.random_greedy(100, 0.3, 4),     # order 100, 30 % prefilled
         "planted127_60": gen.planted(127, 0.6, 1),          # largest order the boundary accepts
         "greedy127_50": gen.random_greedy(127, 0.5, 1),
     }
