@@ -149,7 +149,10 @@ template <int B>
 __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
     const DistArgs a = arg_of<DistArgs>(L);
     if (a.ctl && a.ctl->stop) return;
-    constexpr int PITCH = kCW * B + 1;  // odd pitch: rows fall in distinct banks
+    // even pitch with 64-bit reads: 16 rows at a pitch of kCW*B + 2 words
+    // (50 for B = 6) start in distinct even banks, so the bank pairs of a
+    // 64-bit read never collide; plane pairs stay 8-byte aligned
+    constexpr int PITCH = (B % 2 == 0) ? kCW * B + 2 : kCW * B + 1;
     constexpr int OPW = 2 * kTile * PITCH;             // operand words
     constexpr int DTW = kTile * (kTile + 2) / 2;       // output tile words
     __shared__ uint32_t AB[OPW > DTW ? OPW : DTW];
@@ -188,13 +191,29 @@ __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
 #pragma unroll 1
         for (int wc = 0; wc < nw; ++wc) {
             uint32_t ra[4][B], rb[4][B];
+            if constexpr (B % 2 == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    ra[i][b] = As[(ty + 16 * i) * PITCH + wc * B + b];
-                    rb[i][b] = Bs[(tx + 16 * i) * PITCH + wc * B + b];
-                }
+                    for (int b = 0; b < B; b += 2) {
+                        const u32x2 x = *reinterpret_cast<const u32x2 *>(
+                            As + (ty + 16 * i) * PITCH + wc * B + b);
+                        const u32x2 y = *reinterpret_cast<const u32x2 *>(
+                            Bs + (tx + 16 * i) * PITCH + wc * B + b);
+                        ra[i][b] = x.x;
+                        ra[i][b + 1] = x.y;
+                        rb[i][b] = y.x;
+                        rb[i][b + 1] = y.y;
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        ra[i][b] = As[(ty + 16 * i) * PITCH + wc * B + b];
+                        rb[i][b] = Bs[(tx + 16 * i) * PITCH + wc * B + b];
+                    }
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
