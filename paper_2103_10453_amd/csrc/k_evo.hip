@@ -175,17 +175,39 @@ __global__ __launch_bounds__(256) void dist_kernel(const ArgList L) {
     for (int w0 = 0; w0 < a.W; w0 += kCW) {
         const int nw = min(kCW, a.W - w0);
         // stage kTile rows x nw words x B planes for both sides
-        for (int q = tid; q < kTile * kCW * B; q += 256) {
-            const int row = q / (kCW * B), rem = q % (kCW * B);
-            const int wc = rem / B;
-            uint32_t va = 0u, vb = 0u;
-            if (wc < nw) {
-                const int ra = r0 + row, rb = c0 + row;
-                if (ra < a.m) va = *gptr(a.planes + ((size_t)ra * a.W + w0) * B + rem);
-                if (rb < a.m) vb = *gptr(a.planes + ((size_t)rb * a.W + w0) * B + rem);
+        if constexpr (B % 2 == 0) {
+            // plane pairs: 8-byte global loads and LDS stores (rows of B
+            // words per vertex word keep pairs 8-byte aligned on both sides)
+            constexpr int HP = kCW * B / 2;  // pairs per staged row
+            for (int q = tid; q < kTile * HP; q += 256) {
+                const int row = q / HP, rem = 2 * (q % HP);
+                const int wc = rem / B;
+                u32x2 va{0u, 0u}, vb{0u, 0u};
+                if (wc < nw) {
+                    const int ra = r0 + row, rb = c0 + row;
+                    if (ra < a.m)
+                        va = *gptr(reinterpret_cast<const u32x2 *>(
+                            a.planes + ((size_t)ra * a.W + w0) * B + rem));
+                    if (rb < a.m)
+                        vb = *gptr(reinterpret_cast<const u32x2 *>(
+                            a.planes + ((size_t)rb * a.W + w0) * B + rem));
+                }
+                *reinterpret_cast<u32x2 *>(As + row * PITCH + rem) = va;
+                *reinterpret_cast<u32x2 *>(Bs + row * PITCH + rem) = vb;
             }
-            As[row * PITCH + rem] = va;
-            Bs[row * PITCH + rem] = vb;
+        } else {
+            for (int q = tid; q < kTile * kCW * B; q += 256) {
+                const int row = q / (kCW * B), rem = q % (kCW * B);
+                const int wc = rem / B;
+                uint32_t va = 0u, vb = 0u;
+                if (wc < nw) {
+                    const int ra = r0 + row, rb = c0 + row;
+                    if (ra < a.m) va = *gptr(a.planes + ((size_t)ra * a.W + w0) * B + rem);
+                    if (rb < a.m) vb = *gptr(a.planes + ((size_t)rb * a.W + w0) * B + rem);
+                }
+                As[row * PITCH + rem] = va;
+                Bs[row * PITCH + rem] = vb;
+            }
         }
         __syncthreads();
 #pragma unroll 1
