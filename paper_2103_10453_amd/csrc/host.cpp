@@ -163,15 +163,17 @@ int max_lds_per_block() { return g_lds_limit; }
 
 // Candidate positions per lane and round in PLITS: the chunk size CH that
 // minimises the modelled evaluation work of one pass over every candidate
-// row, sum_v ceil((d_v + 1) / CH) (CH + 1.5), the 1.5 standing for a chunk's
-// fixed work (descriptor, vertex state, loads) in units of one move.
+// row, sum_v ceil((d_v + 1) / CH) (CH + 3), the 3 standing for a chunk's
+// fixed work (descriptor, vertex state, loads) in units of one move (fitted
+// to measured runs: with 1.5 the model picked 4 for the 70x70 grid 70 %
+// prefilled, which runs 7 % faster with 8).
 int choose_spl(const plse_instance *h) {
     if (h->spl) return h->spl;
     int pick = 4;
     double best = 0.0;
     for (int ch : {2, 4, 8}) {
         double cost = 0.0;
-        for (int v = 0; v < h->nv; ++v) cost += (double)((((h->vinfo[v] >> 16) & 0xFFu) + ch) / ch) * (ch + 1.5);
+        for (int v = 0; v < h->nv; ++v) cost += (double)((((h->vinfo[v] >> 16) & 0xFFu) + ch) / ch) * (ch + 3.0);
         if (ch == 2 || cost < best) {
             best = cost;
             pick = ch;
