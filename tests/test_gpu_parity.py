@@ -589,3 +589,29 @@ def test_c_example_solves_like_the_oracle(torch_cuda, oracle_mod):
     o = I.run(I.params(depth=1440), 24, 3, 17)
     assert int(head[1]) == o["filled"] and int(head[3]) == I.ub and int(head[5]) == o["gens"]
     np.testing.assert_array_equal(grid, o["grid"])
+
+
+def test_select_full_size_parity(torch_cuda, oracle_mod):
+    """Alg. 4 at the benchmark's full size (2p = 32768 candidates, keys sorted
+    in global memory) equals the oracle; candidates fall in clusters of about
+    five mutually close ones (D within the spacing), the rest far apart."""
+    g = gen.random_greedy(20, 0.5, 7)
+    s = P.Solver(g)
+    I = oracle_mod.Instance(g)
+    p = 16384
+    m = 2 * p
+    _say(f"select full size m={m}")
+    rng = np.random.default_rng(5)
+    cl = rng.integers(0, 6000, size=m)
+    D = np.empty((m, m), dtype=np.int16)
+    for r0 in range(0, m, 4096):
+        D[r0:r0 + 4096] = np.where(cl[r0:r0 + 4096, None] == cl[None, :], np.int16(4),
+                                   np.int16(90))
+    np.fill_diagonal(D, 0)
+    f = rng.integers(0, 40, size=m).astype(np.int32)
+    import torch
+    Dg = torch.from_numpy(D).cuda()
+    for gen_no in (1, 7):
+        acc = s.stage_select(torch.from_numpy(f).cuda(), Dg, gen_no, 11)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(_np(acc), oracle_mod.select(I.nv, p, 10, 11, gen_no, f, D))
