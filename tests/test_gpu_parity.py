@@ -615,3 +615,45 @@ def test_select_full_size_parity(torch_cuda, oracle_mod):
         acc = s.stage_select(torch.from_numpy(f).cuda(), Dg, gen_no, 11)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(_np(acc), oracle_mod.select(I.nv, p, 10, 11, gen_no, f, D))
+
+
+def test_generation_stages_full_size(torch_cuda, oracle_mod):
+    """Distances, matching and AUX at the n=50 workload's full size (p = 16384,
+    2p = 32768 rows of 1250 vertices): sampled rows of D recomputed by the
+    oracle, and the whole matching and crossover of the population."""
+    w = gen.workload_n50()
+    g = w["grid"]
+    s = P.Solver(g, depth=w["depth"])
+    I = oracle_mod.Instance(g)
+    p = 16384
+    m = 2 * p
+    _say(f"generation stages full size p={p}")
+    rng = np.random.default_rng(8)
+    S = np.zeros((m, s.stride), dtype=np.uint8)
+    S[:, :I.nv] = rng.integers(0, I.n + 1, size=(m, I.nv), dtype=np.uint8)
+    for t in range(2000):  # near copies, so that distances span the range
+        a, b = rng.integers(0, m, size=2)
+        S[b, :I.nv] = S[a, :I.nv]
+        S[b, rng.integers(0, I.nv, size=int(rng.integers(0, 40)))] = 0
+    import torch
+    D = s.stage_distances(torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 63, 64, 4097, 16383, 16384, 20000, 32767])
+    Dr = _np(D[torch.from_numpy(rows).cuda()]).astype(np.int32)
+    np.testing.assert_array_equal(Dr, oracle_mod.distances(S[rows, :I.nv], S[:, :I.nv]))
+    # matching among the first p rows, empty histories
+    Dp = D[:p, :p].contiguous()
+    uid = (np.arange(p, dtype=np.uint64) + (3 << 32)).astype(np.uint64)
+    hist = np.zeros((p, 64), dtype=np.uint64)
+    hc = np.zeros(p, dtype=np.int32)
+    hist_t = torch.from_numpy(hist.view(np.int64)).cuda()
+    hc_t = torch.from_numpy(hc).cuda()
+    partner, dpart = s.stage_match(Dp, torch.from_numpy(uid.view(np.int64)).cuda(), hist_t, hc_t)
+    torch.cuda.synchronize()
+    po, do, ho, hco = oracle_mod.match(_np(Dp).astype(np.int32), uid, hist, hc)
+    np.testing.assert_array_equal(_np(partner), po)
+    np.testing.assert_array_equal(_np(dpart), do)
+    # AUX offspring of the whole population
+    out = s.stage_aux(torch.from_numpy(S[:p]).cuda(), partner, dpart, 2, 77)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(out)[:, :I.nv], oracle_mod.aux(77, 2, S[:p, :I.nv], po, do))
