@@ -155,6 +155,8 @@ def main():
                     help="batch: pick each instance's launch shape by measurement first")
     ap.add_argument("--requests", type=int, default=16, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
+    ap.add_argument("--max-slots", type=int, default=64,
+                    help="served: requests resident at once (admission limit)")
     ap.add_argument("--generations", type=int, default=0,
                     help="served: generations per request (default 50)")
     ap.add_argument("--hw-queues", type=int, default=16,
@@ -391,7 +393,7 @@ def bench_served(args, gen, plse):
     p = reqs[0]["population"]
     budget = int(0.6 * torch.cuda.get_device_properties(0).total_memory)
     # served: submit at arrival times, poll until all are done
-    srv = plse.Server(budget, max_slots=64)
+    srv = plse.Server(budget, max_slots=args.max_slots)
     solvers = [plse.Solver(r["grid"], depth=r["depth"]) for r in reqs]
     tickets, results = [], {}
     t0 = time.perf_counter()
@@ -436,7 +438,8 @@ def bench_served(args, gen, plse):
         "config": {"workload": "served: n ~ U{10..100}, r ~ U[0.3, 0.7], planted or "
                                "random-greedy, population 2048, depth 10n^2",
                    "requests": len(reqs), "rate": args.rate, "generations": G,
-                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+                   "max_slots": args.max_slots},
         "moves_per_s": moves / wall,
         "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "time_to_best_s": {"p50": pct(ttb, 50), "p99": pct(ttb, 99)},
