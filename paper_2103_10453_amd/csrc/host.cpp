@@ -792,7 +792,7 @@ int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &o
     }
     for (size_t i = 0; i < S.hs.size(); ++i) {
         plse_instance *h = S.hs[i];
-        const int gens = ctl[i].gens_run;
+        const int gens = std::min(ctl[i].gens_run, G);  // every stepped generation has ended
         h->gen_best.assign((size_t)gens, 0);
         h->gen_cnt.assign((size_t)gens * kCounters, 0);
         plse_stats &ls = h->last;
@@ -1589,9 +1589,13 @@ struct Request {
 int collect(Request &r, hipStream_t s) {
     plse_instance *h = r.h;
     Ctl c{};
-    std::vector<GenStat> gs((size_t)std::max(r.steps, 1));
-    std::vector<uint8_t> star((size_t)h->stride);
+    // the control block first: generations may have run beyond the last one
+    // the worker saw end (a request cancelled with generations queued)
     HIP_TRY(hipMemcpyAsync(&c, at<Ctl>(h, h->L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c.gens_run < 0 || c.gens_run > PLSE_MAX_GENERATIONS) return PLSE_E_HIP;
+    std::vector<GenStat> gs((size_t)std::max(c.gens_run, 1));
+    std::vector<uint8_t> star((size_t)h->stride);
     HIP_TRY(hipMemcpyAsync(gs.data(), at<GenStat>(h, h->L.stats), sizeof(GenStat) * gs.size(),
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(star.data(), at<uint8_t>(h, h->L.Sstar), h->stride,
@@ -1614,6 +1618,7 @@ int collect(Request &r, hipStream_t s) {
     h->last.stop_reason = c.stop_reason;
     r.best_gen = c.best_gen;
     r.moves = h->last.totals[C_MOVES];
+    r.steps = std::max(r.steps, gens);  // generations run, seen ending or not
     const int n = h->n;
     r.grid.assign((size_t)n * n, 0);
     int cnt = 0;
