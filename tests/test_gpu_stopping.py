@@ -249,6 +249,14 @@ def test_server_cancel_waiting_and_resident_requests(torch_cuda):
         assert r1["status"] == P.PLSE_E_CANCELLED
         assert 1 <= r1["generations"] < 500
         assert gen.is_partial_latin(r1["grid"]) and 0 < r1["filled"] <= long.ub
+        # the statistics cover every generation the request ran, including
+        # those still queued when it was cancelled
+        st = long.stats()
+        assert st["generations_run"] == r1["generations"]
+        bf = st["best_f_per_gen"]
+        assert len(bf) == r1["generations"] and np.all(np.diff(bf) <= 0)
+        assert np.all(st["counters_per_gen"][:, 0] > 0)
+        assert long.n * long.n - long.l - int(bf[-1]) == r1["filled"]
         for t in (t1, 12345):
             with pytest.raises(P.PlseError) as e:
                 srv.cancel(t)
