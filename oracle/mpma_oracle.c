@@ -377,9 +377,15 @@ static void plits_phase(const inst_t *I, const int64_t *P, uint64_t seed, uint32
             if (old) W->conf[(size_t)u * (n + 1) + old]--;
             if (bk) W->conf[(size_t)u * (n + 1) + bk]++;
         });
-        /* work counter: the move changes the row and column counts of the
-         * colour it leaves and of the colour it takes */
-        cnt[ORC_C_NUPD] += 2u * (old != 0) + 2u * (bk != 0);
+        /* work counters: the conflict-table entries of every neighbour, for
+         * the colour left and for the colour taken; and, in the factored form
+         * of the table, the row and column counts of those two colours */
+        {
+            uint64_t deg = 0;
+            FOR_NEIGHBOURS(I, bv, u, { (void)u; deg++; });
+            cnt[ORC_C_NUPD] += deg * (uint64_t)((old != 0) + (bk != 0));
+        }
+        cnt[ORC_C_CUPD] += 2u * (old != 0) + 2u * (bk != 0);
         S[bv] = (uint8_t)bk;
         f += (bk == 0) - (old == 0);
         c += dc;
@@ -489,19 +495,22 @@ static void partialcol(const inst_t *I, const int64_t *P, uint64_t seed, uint32_
         }
         /* bv joins class bk; its neighbours in class bk leave it */
         int ng = 0;
+        uint64_t upd = 0;
         FOR_NEIGHBOURS(I, bv, u, {
             if (S[u] == bk) gone[ng++] = u;
             W->conf[(size_t)u * (n + 1) + bk]++;
+            upd++;
         });
         S[bv] = (uint8_t)bk;
         for (int q = 0; q < ng; q++) {
             int u = gone[q];
             S[u] = 0;
-            FOR_NEIGHBOURS(I, u, x, { W->conf[(size_t)x * (n + 1) + bk]--; });
+            FOR_NEIGHBOURS(I, u, x, { W->conf[(size_t)x * (n + 1) + bk]--; upd++; });
         }
         die_if(ng - 1 != bdelta);
         f += bdelta;
-        cnt[ORC_C_NUPD] += 2u + 2u * (uint64_t)ng;
+        cnt[ORC_C_NUPD] += upd;
+        cnt[ORC_C_CUPD] += 2u + 2u * (uint64_t)ng;
         if (P[ORC_P_PARANOID]) {
             int64_t f2, c2;
             int *conf2 = (int *)malloc(sizeof(int) * (size_t)nv * (n + 1));
@@ -690,15 +699,23 @@ void orc_match(int32_t p, const int32_t *D, const uint64_t *uid, uint64_t *hist,
 /* the integer threshold floor((beta*D - |V|) * 2^32 / (beta*D)) on a 32-bit */
 /* draw, and 0 when beta*D <= |V|.                                          */
 /* ------------------------------------------------------------------------ */
+uint64_t orc_aux_threshold(int64_t beta_num, int64_t beta_den, int32_t D, int32_t nv) {
+    /* p_ij = 1 - |V| / (beta D) = (beta_num D - beta_den |V|) / (beta_num D),
+     * scaled by 2^32; the numerator times 2^32 needs more than 64 bits for
+     * large beta terms, so the division is done in 128 bits */
+    uint64_t bd = (uint64_t)beta_num * (uint64_t)D;
+    uint64_t bv = (uint64_t)beta_den * (uint64_t)nv;
+    if (bd <= bv) return 0;
+    return (uint64_t)((((unsigned __int128)(bd - bv)) << 32) / bd);
+}
+
 void orc_aux_mode(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num,
                   int64_t beta_den, int32_t mode, const uint8_t *S, const int32_t *partner,
                   const int32_t *dpart, uint8_t *S_off) {
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < p; i++) {
         int j = partner[i];
-        uint64_t bd = (uint64_t)beta_num * (uint64_t)dpart[i];
-        uint64_t bv = (uint64_t)beta_den * (uint64_t)nv;
-        uint64_t thr = (bd <= bv) ? 0 : (((bd - bv) << 32) / bd);
+        uint64_t thr = orc_aux_threshold(beta_num, beta_den, dpart[i], nv);
         /* UX: p_ij fixed at 1/2 (Section 3.5.2); no crossover: the offspring
          * is a copy of its first parent (Section 5.2) */
         if (mode == ORC_X_UX) thr = 1ull << 31;
@@ -724,6 +741,14 @@ void orc_aux(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t beta_num
 int32_t orc_run(const void *h, const int64_t *P, int32_t p, int32_t G, uint64_t seed,
                 int8_t *grid_out, int32_t *filled, int32_t *best_f_gen,
                 uint64_t *counters_gen, uint8_t *final_S, int32_t *final_f) {
+    return orc_run_state(h, P, p, G, seed, grid_out, filled, best_f_gen, counters_gen, final_S,
+                         final_f, NULL);
+}
+
+int32_t orc_run_state(const void *h, const int64_t *P, int32_t p, int32_t G, uint64_t seed,
+                      int8_t *grid_out, int32_t *filled, int32_t *best_f_gen,
+                      uint64_t *counters_gen, uint8_t *final_S, int32_t *final_f,
+                      const orc_state_t *state) {
     const inst_t *I = (const inst_t *)h;
     int n = I->n, nv = I->nv, m = 2 * p;
     if (p < 2 || G < 1) return -1;
@@ -822,6 +847,13 @@ int32_t orc_run(const void *h, const int64_t *P, int32_t p, int32_t G, uint64_t 
     *filled = fl;
     if (final_S) memcpy(final_S, Sall, (size_t)p * snv);
     if (final_f) memcpy(final_f, fall, sizeof(int32_t) * p);
+    if (state) {
+        if (state->uid) memcpy(state->uid, uid, sizeof(uint64_t) * p);
+        if (state->hist) memcpy(state->hist, hist, sizeof(uint64_t) * (size_t)p * ORC_HMAX);
+        if (state->hcount) memcpy(state->hcount, hc, sizeof(int32_t) * p);
+        if (state->offspring) memcpy(state->offspring, Soff, (size_t)p * snv);
+        if (state->best) memcpy(state->best, Sstar, snv);
+    }
 
     free(Sall); free(Snext); free(Soff); free(Sstar); free(fall); free(fnext); free(uid);
     free(uidn); free(hist); free(histn); free(hc); free(hcn); free(Dall); free(Dn); free(acc);

@@ -29,11 +29,21 @@
  *   orc_aux        closed-form expected distances of Section 3.5.2; UX keeps
  *                  half the differing positions (binomial bound); no
  *                  crossover copies the first parent exactly.
- *   orc_run        filled <= UB; planted instances complete; brute-force
+ *   counters       every counter of a search re-derived from the brute-force
+ *                  move trace (iterations, moves, idle, candidates, eligible
+ *                  vertices, neighbour and count updates, snapshots).
+ *   orc_run        a literal transcription of Alg. 2 (tests/refdefs.py) on
+ *                  tiny grids: final population, f, uids, partner
+ *                  histories, offspring, S* and best f per generation equal;
+ *                  planted slips in the bookkeeping (history dropped, uids
+ *                  by rank, transposed distances, first offspring) fail it.
+ *                  filled <= UB; planted instances complete; brute-force
  *                  optimum on tiny grids; with an iteration cap, the stop
  *                  generation is the first whose cumulative count reaches the
  *                  cap (fixed per-generation count on a hard instance) and the
  *                  capped run is a prefix of the uncapped one.
+ *   AUX threshold  exact big-integer Eq. 9 threshold, also where
+ *                  (beta D - |V|) 2^32 exceeds 64 bits.
  */
 #ifndef MPMA_ORACLE_H
 #define MPMA_ORACLE_H
@@ -81,10 +91,15 @@ enum {
     ORC_C_IDLE,         /* iterations with no admissible candidate               */
     ORC_C_CANDS,        /* candidate one-moves examined                          */
     ORC_C_ELIG,         /* eligible vertices, summed over iterations             */
-    ORC_C_NUPD,         /* row/column colour counts changed by moves (2 per      */
-                        /* coloured end of a move: colour left, colour taken)    */
+    ORC_C_NUPD,         /* conflict-table entries updated by moves: the          */
+                        /* incremental evaluation of Section 3.3 changes         */
+                        /* conf[u][old] and conf[u][new] of every neighbour u    */
+                        /* of the moved vertex, one entry per coloured end       */
     ORC_C_SNAPS,        /* best-solution snapshots                               */
     ORC_C_REPAIRS,      /* vertices uncoloured by the final repair               */
+    ORC_C_CUPD,         /* row/column colour counts changed by moves (2 per      */
+                        /* coloured end: the factored form of the same table,    */
+                        /* conf[v][k] = row count + column count - 2[S(v) = k])  */
     ORC_NCOUNTERS
 };
 
@@ -150,6 +165,28 @@ void orc_aux_mode(int32_t nv, int32_t p, uint64_t seed, int32_t gen, int64_t bet
 int32_t orc_run(const void *h, const int64_t *params, int32_t p, int32_t G, uint64_t seed,
                 int8_t *grid_out, int32_t *filled, int32_t *best_f_gen,
                 uint64_t *counters_gen, uint8_t *final_S, int32_t *final_f);
+
+/* State of Alg. 2 after a run, for comparison at a generation boundary: the
+ * uids, partner histories (ring of ORC_HMAX, write position hcount % hlen,
+ * see orc_match) and their counts of the final population, the offspring
+ * waiting for the next search (p*|V|) and S* (|V|).  Any pointer may be
+ * NULL.  After an early stop (bound or budget) the population is the one
+ * the stopping generation started from. */
+typedef struct {
+    uint64_t *uid;
+    uint64_t *hist;
+    int32_t *hcount;
+    uint8_t *offspring;
+    uint8_t *best;
+} orc_state_t;
+int32_t orc_run_state(const void *h, const int64_t *params, int32_t p, int32_t G, uint64_t seed,
+                      int8_t *grid_out, int32_t *filled, int32_t *best_f_gen,
+                      uint64_t *counters_gen, uint8_t *final_S, int32_t *final_f,
+                      const orc_state_t *state);
+
+/* AUX threshold of Eq. 9 on a 32-bit draw: floor((beta D - |V|) 2^32 /
+ * (beta D)) with beta = beta_num / beta_den, 0 when beta D <= |V|. */
+uint64_t orc_aux_threshold(int64_t beta_num, int64_t beta_den, int32_t D, int32_t nv);
 
 #ifdef __cplusplus
 }

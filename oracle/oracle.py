@@ -23,8 +23,8 @@ X_AUX, X_UX, X_NONE = 0, 1, 2        # crossover variants (Section 3.5.2, Sectio
 M_NEAREST, M_RANDOM = 0, 1           # matching variants (Section 3.5.1, Section 5.3)
 V_MPMA, V_PARTIAL = 0, 1             # MPMA, Partial-MPMA (Section 3.7)
 
-NCOUNTERS = 8
-COUNTER_NAMES = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs"]
+NCOUNTERS = 9
+COUNTER_NAMES = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs", "cupd"]
 HMAX = 64
 
 
@@ -74,6 +74,10 @@ def lib():
                                    P, P, P]
         L.orc_run.restype = i32
         L.orc_run.argtypes = [P, P, i32, i32, u64, P, P, P, P, P, P]
+        L.orc_run_state.restype = i32
+        L.orc_run_state.argtypes = [P, P, i32, i32, u64, P, P, P, P, P, P, P]
+        L.orc_aux_threshold.restype = u64
+        L.orc_aux_threshold.argtypes = [ctypes.c_int64, ctypes.c_int64, i32, i32]
         _lib = L
     return _lib
 
@@ -205,6 +209,31 @@ class Instance:
         return dict(grid=grid, filled=int(filled[0]), best_f=bf, counters=cnt, gens=int(gens),
                     final_S=fS, final_f=ff)
 
+    def run_state(self, params, p: int, G: int, seed: int):
+        """run() plus the state of Alg. 2 at the end: uids, partner histories
+        (ring of HMAX per individual) and their counts, the offspring waiting
+        for the next search, and S*."""
+        grid = np.zeros((self.n, self.n), dtype=np.int8)
+        filled = np.zeros(1, dtype=np.int32)
+        bf = np.zeros(G, dtype=np.int32)
+        cnt = np.zeros((G, NCOUNTERS), dtype=np.uint64)
+        fS = np.zeros((p, self.nv), dtype=np.uint8)
+        ff = np.zeros(p, dtype=np.int32)
+        uid = np.zeros(p, dtype=np.uint64)
+        hist = np.zeros((p, HMAX), dtype=np.uint64)
+        hc = np.zeros(p, dtype=np.int32)
+        off = np.zeros((p, self.nv), dtype=np.uint8)
+        best = np.zeros(max(self.nv, 1), dtype=np.uint8)
+        st = (ctypes.c_void_p * 5)(*[a.ctypes.data for a in (uid, hist, hc, off, best)])
+        P = np.ascontiguousarray(params, dtype=np.int64)
+        gens = lib().orc_run_state(self.h, _ptr(P), p, G, seed, _ptr(grid), _ptr(filled),
+                                   _ptr(bf), _ptr(cnt), _ptr(fS), _ptr(ff), ctypes.byref(st))
+        if gens < 0:
+            raise ValueError("bad run arguments")
+        return dict(grid=grid, filled=int(filled[0]), best_f=bf, counters=cnt, gens=int(gens),
+                    final_S=fS, final_f=ff, uid=uid, hist=hist, hcount=hc, offspring=off,
+                    best=best[: self.nv])
+
 
 def distances(A, B) -> np.ndarray:
     A = np.ascontiguousarray(A, dtype=np.uint8)
@@ -235,6 +264,10 @@ def match(D, uid, hist, hcount, hlen: int = 64, mode: int = M_NEAREST, seed: int
     lib().orc_match_mode(p, _ptr(D), _ptr(uid), _ptr(hist), _ptr(hcount), hlen, mode, seed, gen,
                          _ptr(partner), _ptr(dpart))
     return partner, dpart, hist, hcount
+
+
+def aux_threshold(beta_num: int, beta_den: int, D: int, nv: int) -> int:
+    return int(lib().orc_aux_threshold(beta_num, beta_den, D, nv))
 
 
 def aux(seed: int, gen: int, S, partner, dpart, beta_num: int = 20, beta_den: int = 1,

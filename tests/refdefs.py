@@ -113,14 +113,25 @@ def brute_force_optimum(grid):
 
 
 # --- PLITS re-derived by brute force (Section 3.3, Alg. 3) ------------------------
-def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
+COUNTERS = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs", "cupd"]
+
+
+def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2, counters=None):
     """Every iteration's chosen move, re-derived by evaluating F(S') from scratch
-    for every neighbour S' of N(S) = N_0(S) u N_c(S).  Returns (rows, S_out)."""
+    for every neighbour S' of N(S) = N_0(S) u N_c(S).  Returns (rows, S_out).
+
+    counters (a dict, optional) receives the work counts by their definitions:
+    iterations with a non-empty neighbourhood, moves, idle iterations, the
+    candidate moves examined and eligible vertices per iteration, the
+    conflict-table entries a move changes (one per neighbour of the moved
+    vertex and coloured end, Section 3.3), the row/column counts it changes
+    (two per coloured end), best snapshots and repair uncolourings."""
     verts, dom, _ = reduced_graph(grid)
     n = len(grid)
     nv = len(verts)
     S = list(S_in)
     rows = []
+    cnt = {k: 0 for k in COUNTERS}
     for phase, iters in ((1, depth1), (2, depth2)):
         phi = Fraction(1, 2) if phase == 1 else Fraction(nv)
         scale = 2 if phase == 1 else 1  # F is compared as scale * (f + phi c)
@@ -136,6 +147,8 @@ def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
             elig = [v for v in range(nv) if S[v] == 0 or conflicting(S, verts, v)]
             if not elig:
                 break
+            cnt["iters"] += 1
+            cnt["elig"] += len(elig)
             w = draw(seed, slot, gen, tag, it)
             Fc = F(S)
             best = None
@@ -143,6 +156,7 @@ def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
                 for k in [0] + dom[v]:
                     if k == S[v]:
                         continue
+                    cnt["cands"] += 1
                     S2 = list(S)
                     S2[v] = k
                     delta = F(S2) - Fc
@@ -153,10 +167,15 @@ def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
                         best = (key, v, k, delta)
             if best is None:
                 rows.append((phase, it, -1, -1, 0, Fc, 1))
+                cnt["idle"] += 1
                 continue
             _, v, k, delta = best
             old = S[v]
             S[v] = k
+            ends = int(old != 0) + int(k != 0)
+            cnt["moves"] += 1
+            cnt["nupd"] += ends * sum(1 for u in range(nv) if adjacent(verts[u], verts[v]))
+            cnt["cupd"] += 2 * ends
             mp = sum(1 for u in range(nv) if S[u] == 0 or conflicting(S, verts, u))
             T = ((w[0] * 10) >> 32) + (6 * mp) // 10
             tabu[(v, old)] = it + 1 + T
@@ -165,6 +184,7 @@ def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
             if Fn < Fbest:
                 Fbest = Fn
                 Sbest = list(S)
+                cnt["snaps"] += 1
         S = Sbest
     # final legality guard (Section 3.7): uncolour the most conflicting vertex first
     while True:
@@ -174,6 +194,9 @@ def plits_trace_bruteforce(grid, S_in, seed, slot, gen, depth1, depth2):
         if m == 0:
             break
         S[cnts.index(m)] = 0
+        cnt["repairs"] += 1
+    if counters is not None:
+        counters.update(cnt)
     return rows, S
 
 
@@ -269,3 +292,92 @@ def alg4_literal(f_all, D_all, nv, p, gamma, seed, gen):
             break
         P_next.append(x)
     return P_next
+
+
+# --- Initial population (Section 3.2, reading A), from its definition --------------
+def init_literal(grid, seed, slot):
+    """Randomised greedy legal colouring: vertices in the order of their
+    INIT_ORDER draws (ties by id), each takes the colour of D*(v) unused by its
+    already coloured neighbours drawn by INIT_PICK, or stays uncoloured."""
+    verts, dom, _ = reduced_graph(grid)
+    nv = len(verts)
+    order = sorted(range(nv), key=lambda v: (draw(seed, slot, 0, 0x01, v >> 2)[v & 3], v))
+    S = [0] * nv
+    for t, v in enumerate(order):
+        legal = [k for k in dom[v]
+                 if not any(S[u] == k and adjacent(verts[u], verts[v]) for u in range(nv))]
+        if legal:
+            S[v] = legal[(draw(seed, slot, 0, 0x02, t)[0] * len(legal)) >> 32]
+    return S
+
+
+def aux_threshold_exact(beta_num, beta_den, D, nv):
+    """Eq. 9 scaled to a 32-bit draw: floor(p_ij 2^32) with p_ij = 1 - |V| / (beta D),
+    beta = beta_num / beta_den; 0 when p_ij <= 0 (reading R).  Exact rationals."""
+    if D == 0:
+        return 0
+    pij = 1 - Fraction(nv * beta_den, beta_num * D)
+    if pij <= 0:
+        return 0
+    return (pij.numerator << 32) // pij.denominator
+
+
+# --- The memetic algorithm, Alg. 2, transcribed literally --------------------------
+def mpma_literal(grid, p, G, seed, depth1, depth2, hist_len=64, beta=(20, 1), gamma=10):
+    """Alg. 2 step by step on lists.  P_1 = randomised greedy colourings; in
+    generation 1 the offspring are P_1 itself.  Each generation: PLITS on every
+    offspring (slot i, generation g), best-solution saving (lowest slot among
+    equal f, strict improvement), distances over P_t then P', Alg. 4, uids
+    (initial individuals: their slot; offspring of generation g: g << 32 | slot;
+    survivors keep theirs), nearest-neighbour matching that skips the uids of
+    recent partners (history of the last hist_len partners, oldest dropped
+    first, carried by the individual; offspring start with an empty one; the
+    filter is dropped when it excludes everyone) and the AUX crossover.
+    Returns the final population with f, uids, histories (oldest first), the
+    offspring waiting for the next search, S* and the best f per generation."""
+    import numpy as np
+
+    verts, dom, _ = reduced_graph(grid)
+    nv = len(verts)
+    P = [init_literal(grid, seed, i) for i in range(p)]
+    f = [f_of(S) for S in P]
+    uid = list(range(p))
+    hist = [[] for _ in range(p)]
+    O = [list(S) for S in P]
+    star, fstar, best_f = None, None, []
+    for g in range(1, G + 1):
+        Pp = [plits_trace_bruteforce(grid, O[i], seed, i, g, depth1, depth2)[1] for i in range(p)]
+        fp = [f_of(S) for S in Pp]
+        b = min(range(p), key=lambda i: (fp[i], i))
+        if fstar is None or fp[b] < fstar:
+            fstar, star = fp[b], list(Pp[b])
+        best_f.append(fstar)
+        A = P + Pp
+        fa = f + fp
+        D = [[sum(1 for v in range(nv) if A[x][v] != A[y][v]) for y in range(2 * p)]
+             for x in range(2 * p)]
+        acc = alg4_literal(fa, D, nv, p, gamma, seed, g)
+        uid_all = uid + [(g << 32) | i for i in range(p)]
+        hist_all = hist + [[] for _ in range(p)]
+        P = [list(A[x]) for x in acc]
+        f = [fa[x] for x in acc]
+        uid = [uid_all[x] for x in acc]
+        hist = [list(hist_all[x]) for x in acc]
+        Dn = np.array([[D[acc[i]][acc[j]] for j in range(p)] for i in range(p)])
+        partner = []
+        for i in range(p):
+            allowed = np.array([j != i and uid[j] not in hist[i] for j in range(p)])
+            if not allowed.any():
+                allowed = np.array([j != i for j in range(p)])
+            j = int(np.argmin(np.where(allowed, Dn[i], np.iinfo(np.int64).max)))
+            partner.append(j)
+            if hist_len > 0:
+                hist[i].append(uid[j])
+                if len(hist[i]) > hist_len:
+                    hist[i].pop(0)
+        O = []
+        for i, j in enumerate(partner):
+            thr = aux_threshold_exact(beta[0], beta[1], int(Dn[i][j]), nv)
+            O.append([P[i][v] if draw(seed, i, g, 0x31, v >> 2)[v & 3] < thr else P[j][v]
+                      for v in range(nv)])
+    return dict(P=P, f=f, uid=uid, hist=hist, O=O, star=star, best_f=best_f)

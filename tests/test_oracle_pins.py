@@ -248,7 +248,7 @@ def test_plits_incremental_state_equals_recomputation(oracle_mod, n, r, planted,
     for i in range(6):
         assert R.c_of(list(S_out[i]), verts) == 0
         assert f[i] == R.f_of(list(S_out[i]))
-    names = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs"]
+    names = oracle_mod.COUNTER_NAMES
     c = dict(zip(names, cnt.sum(0)))
     assert c["moves"] + c["idle"] == c["iters"]
     assert c["cands"] >= c["iters"] and c["elig"] >= c["iters"]
