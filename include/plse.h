@@ -39,9 +39,13 @@ typedef struct plse_instance *plse_handle;
 /* Number of per-generation counters reported by plse_last_stats and the
  * per-individual counter rows of plse_stage_plits, in this order:
  * iterations, moves, idle iterations, candidates examined, eligible vertices
- * (summed over iterations), conflict-table entries updated, best-solution
- * snapshots, vertices uncoloured by the final repair. */
-#define PLSE_NCOUNTERS 8
+ * (summed over iterations), conflict-table entries updated (the incremental
+ * evaluation of Section 3.3 changes the entries of every neighbour of the
+ * moved vertex, once per coloured end), best-solution snapshots, vertices
+ * uncoloured by the final repair, row/column colour counts updated (the
+ * factored form of the same table this library keeps: two per coloured
+ * end). */
+#define PLSE_NCOUNTERS 9
 #define PLSE_MAX_GENERATIONS 65536
 #define PLSE_MAX_POPULATION 32768
 #define PLSE_HIST 64

@@ -74,6 +74,16 @@ __host__ __device__ inline int32_t squeezed_bound(int32_t dfg, int32_t dcg, int3
     return 4 * q + (r < 2 ? r : 2);
 }
 
+// floor(x 2^32 / y) for x < y < 2^47 (the Eq. 9 threshold: x = beta_num D -
+// beta_den |V|, y = beta_num D, both below 2^35 for the parameter ranges),
+// by two 16-bit steps of long division so no product exceeds 64 bits.
+__host__ __device__ inline uint64_t frac_shift32(uint64_t x, uint64_t y) {
+    const uint64_t a = x << 16;
+    const uint64_t q1 = a / y, r1 = a - q1 * y;
+    const uint64_t q0 = (r1 << 16) / y;
+    return (q1 << 16) | q0;
+}
+
 // floor(w * m / 2^32): uniform integer in [0, m).
 __device__ __forceinline__ uint32_t scale32(uint32_t w, uint32_t m) { return __umulhi(w, m); }
 

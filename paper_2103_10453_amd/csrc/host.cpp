@@ -1174,6 +1174,8 @@ struct CkptHeader {
     int32_t gens_run, pad;
 };
 constexpr uint32_t kCkptMagic = 0x4B534C50u;  // "PLSK"
+// 2: nine counters per generation record
+constexpr uint32_t kCkptVersion = 2u;
 
 // FNV-1a over the grid and every parameter that shapes a run.
 uint64_t run_ident(const plse_instance *h) {
@@ -1231,7 +1233,7 @@ int plse_checkpoint(plse_handle h, void *stream, void *buf, size_t capacity, siz
     *bytes = ckpt_bytes(parts);
     if (!buf) return PLSE_OK;
     if (capacity < *bytes) return PLSE_E_ARG;
-    CkptHeader hd{kCkptMagic, 1u, h->n, h->nv, h->stride, S.p, S.seed, run_ident(h),
+    CkptHeader hd{kCkptMagic, kCkptVersion, h->n, h->nv, h->stride, S.p, S.seed, run_ident(h),
                   c.gens_run, 0};
     uint8_t *out = static_cast<uint8_t *>(buf);
     std::memcpy(out, &hd, sizeof(hd));
@@ -1249,7 +1251,7 @@ int plse_resume(plse_handle h, int32_t p, void *stream, const void *buf, size_t 
     if (!h || !buf || bytes < sizeof(CkptHeader)) return PLSE_E_ARG;
     CkptHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (hd.magic != kCkptMagic || hd.version != 1u || hd.n != h->n || hd.nv != h->nv ||
+    if (hd.magic != kCkptMagic || hd.version != kCkptVersion || hd.n != h->n || hd.nv != h->nv ||
         hd.stride != h->stride || hd.p != p || hd.ident != run_ident(h) || hd.gens_run < 0 ||
         hd.gens_run > PLSE_MAX_GENERATIONS)
         return PLSE_E_ARG;

@@ -819,7 +819,7 @@ __global__ __launch_bounds__(256) void aux_kernel(const ArgList L) {
     // copies its first parent (Section 5.2)
     const uint64_t thr = a.mode == 1   ? (1ull << 31)
                          : a.mode == 2 ? (1ull << 32)
-                                       : ((bd <= bv) ? 0ull : (((bd - bv) << 32) / bd));
+                                       : ((bd <= bv) ? 0ull : frac_shift32(bd - bv, bd));
     const uint32_t *si = reinterpret_cast<const uint32_t *>(a.S + (size_t)i * a.stride);
     const uint32_t *sj = reinterpret_cast<const uint32_t *>(a.S + (size_t)j * a.stride);
     uint32_t *so = reinterpret_cast<uint32_t *>(a.S_off + (size_t)i * a.stride);

@@ -66,7 +66,7 @@ struct WaveState {
 // bits; eligible-vertex and update sums take 64.
 struct Cnt {
     uint32_t iters, idle, snaps, repairs;
-    uint64_t elig, nupd;
+    uint64_t elig, nupd, cupd;
 };
 
 struct Scal {
@@ -495,16 +495,20 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
             }
             sc.f += cvk - 1;
             sc.F = sc.f;
-            ucnt.nupd += 2u + 2u * (uint32_t)cvk;
+            ucnt.cupd += 2u + 2u * (uint32_t)cvk;
             const uint32_t mp = (uint32_t)sc.f;
             const uint32_t T = scale32(w0, 10u) + udiv_by(alpha_n * mp, alpha_d, m_alpha);
             const uint32_t until = itu + 1u + T;
             PLSE_WAVE_SYNC();
+            // conflict-table entries: v's neighbours, then each uncoloured
+            // vertex's neighbours
+            uint32_t nupd_l = 0u;
             for (int t0 = 0; t0 < deg; t0 += 64) {
                 const int t = t0 + lane;
                 const uint32_t ent = t0 == 0 ? ent0 : (t < deg ? gptr(nb)[t] : 0u);
                 const int u = (int)(ent & 0xFFFFu), other = (int)((ent >> 16) & 0x7FFFu);
                 if (t < deg && ws.S[u] == k) {
+                    nupd_l += gptr(I.vinfo)[u] >> 24;
                     const bool inrow = (ent >> 31) == 0;
                     const int ur = inrow ? r : other, uc = inrow ? other : c;
                     const int rb = ur * np1 + k, cb = n * np1 + uc * np1 + k;
@@ -527,6 +531,7 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
                     if (mark > ws.tm8[u]) ws.tm8[u] = (uint8_t)mark;
                 }
             }
+            ucnt.nupd += (uint64_t)deg + wave_sum_u32_dpp(nupd_l);
         } else {
             // 4. apply.  Counts: lanes 0-1 the leaving colour's row and column
             //    count (-1), lanes 2-3 the entering colour's (+1), as LDS adds on
@@ -570,7 +575,9 @@ __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
             sc.f += df;
             sc.c += cvk - cvo;
             sc.F += (int64_t)phi_den * df + (int64_t)phi_num * (cvk - cvo);
-            ucnt.nupd += 2u * (old != 0) + 2u * (k != 0);
+            const uint32_t ends = (uint32_t)(old != 0) + (uint32_t)(k != 0);
+            ucnt.cupd += 2u * ends;
+            ucnt.nupd += (uint32_t)deg * ends;
             // tenure T = L + alpha (|V_0| + |C|) after the move; moving v back to
             // `old` is tabu for T iterations
             const uint32_t mp = (uint32_t)(sc.f + sc.nC);
@@ -692,7 +699,7 @@ __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     const uint8_t *src = a.S_in + (size_t)ind * I.stride;
     uint8_t *out = a.S_out + (size_t)ind * I.stride;
 
-    Cnt ucnt{0u, 0u, 0u, 0u, 0ull, 0ull};
+    Cnt ucnt{0u, 0u, 0u, 0u, 0ull, 0ull, 0ull};
     uint32_t lane_cands = 0;
     Scal sc;
     const uint32_t slot = (uint32_t)readfirst(ind);
@@ -729,7 +736,8 @@ __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
             case C_ELIG: v = ucnt.elig; break;
             case C_NUPD: v = ucnt.nupd; break;
             case C_SNAPS: v = ucnt.snaps; break;
-            default: v = ucnt.repairs; break;
+            case C_REPAIRS: v = ucnt.repairs; break;
+            default: v = ucnt.cupd; break;
         }
         gptr(a.cnt_out)[(size_t)ind * kCounters + lane] = v;
     }

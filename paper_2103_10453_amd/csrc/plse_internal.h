@@ -8,11 +8,14 @@
 namespace plse {
 
 constexpr int kHist = 64;        // partner-history slots per individual
-constexpr int kCounters = 8;     // iters, moves, idle, cands, elig, nupd, snaps, repairs
+constexpr int kCounters = 9;     // iters, moves, idle, cands, elig, nupd, snaps, repairs, cupd
 constexpr int kAdj = 32;         // close-neighbour list capacity per candidate (select)
 constexpr uint8_t kNoSlot = 0xFF;
 
-enum Counter { C_ITERS = 0, C_MOVES, C_IDLE, C_CANDS, C_ELIG, C_NUPD, C_SNAPS, C_REPAIRS };
+// nupd: conflict-table entries a move changes (Section 3.3: every neighbour of
+// the moved vertex, once per coloured end); cupd: the row/column counts that
+// hold the same table in factored form (two per coloured end).
+enum Counter { C_ITERS = 0, C_MOVES, C_IDLE, C_CANDS, C_ELIG, C_NUPD, C_SNAPS, C_REPAIRS, C_CUPD };
 
 // Random-stream tags: which decision a Philox draw belongs to.
 enum Tag : uint32_t {

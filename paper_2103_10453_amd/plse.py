@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(HERE, "libplse.so")
 
 PLSE_OK, PLSE_E_ARG, PLSE_E_GRID, PLSE_E_WORKSPACE, PLSE_E_HIP, PLSE_E_BUSY, PLSE_PENDING, \
     PLSE_E_PARAM, PLSE_E_CAPACITY, PLSE_E_FAULT, PLSE_E_CANCELLED = range(11)
-NCOUNTERS = 8
-COUNTER_NAMES = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs"]
+NCOUNTERS = 9
+COUNTER_NAMES = ["iters", "moves", "idle", "cands", "elig", "nupd", "snaps", "repairs", "cupd"]
 HIST = 64
 MAX_GENERATIONS = 65536
 

@@ -1,6 +1,7 @@
 // Host-side check of the pure integer helpers that the tabu-search kernel
 // uses (compiled for the CPU by tests/test_kernel_math.py): magic-number
-// division, the squeezed move scale and its aspiration bound.
+// division, the squeezed move scale and its aspiration bound, and the
+// crossover kernel's threshold division.
 #include <cstdint>
 #include <cstdio>
 #include <random>
@@ -56,6 +57,24 @@ int main() {
                 for (int df = -1; df <= 1; ++df)
                     CHECK(((int64_t)nv * dc + df < thr) == (4 * dc + df < b),
                           "bound nv=%d dfg=%d dcg=%d dc=%d df=%d", nv, dfg, dcg, dc, df);
+        }
+    }
+    // AUX threshold floor(x 2^32 / y), x < y, against 128-bit division: the
+    // whole range of beta_num D (beta_num <= 10^6, D <= 16129)
+    for (int i = 0; i < 2000000; ++i) {
+        const uint64_t y = 1 + rng() % 16129000000ull;
+        const uint64_t x = rng() % y;
+        const uint64_t ref = (uint64_t)((((unsigned __int128)x) << 32) / y);
+        CHECK(frac_shift32(x, y) == ref, "frac %llu/%llu", (unsigned long long)x,
+              (unsigned long long)y);
+    }
+    for (uint64_t y : {1ull, 2ull, 3ull, 1250ull, 25000ull, 4294967295ull, 4294967296ull,
+                       16129000000ull}) {
+        for (uint64_t x : {(uint64_t)0, (uint64_t)1, y / 2, y - 1}) {
+            if (x >= y) continue;
+            const uint64_t ref = (uint64_t)((((unsigned __int128)x) << 32) / y);
+            CHECK(frac_shift32(x, y) == ref, "frac edge %llu/%llu", (unsigned long long)x,
+                  (unsigned long long)y);
         }
     }
     if (fails) {

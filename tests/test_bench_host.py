@@ -42,8 +42,8 @@ def test_traffic_reader_scales_and_checks_the_kernel_hash(tmp_path, monkeypatch)
 
 
 def test_operation_model_counts():
-    # iters, moves, idle, cands, elig, nupd, snaps, repairs
-    cnt = [10, 9, 1, 100, 20, 36, 2, 0]
+    # iters, moves, idle, cands, elig, nupd, snaps, repairs, cupd
+    cnt = [10, 9, 1, 100, 20, 36, 2, 0, 36]
     n, nv = 10, 60
     per_iter = 2 * 2 + 7 * 11 + 10
     per_move = 8 + 3 * 12

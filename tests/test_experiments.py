@@ -10,7 +10,7 @@ from paper_2103_10453_amd import instances as gen
 
 
 def _stats(iters, best_gen, gens=None):
-    cnt = np.zeros((len(iters), 8), dtype=np.uint64)
+    cnt = np.zeros((len(iters), 9), dtype=np.uint64)
     cnt[:, 0] = iters
     return dict(generations_run=gens if gens is not None else len(iters),
                 best_generation=best_gen, counters_per_gen=cnt)
