@@ -113,6 +113,13 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *                 round (default 0: chosen from the domain sizes)
  *   "waves_per_block" 1, 2 or 4: PLITS launch shape (default: chosen from the
  *                 LDS footprint)
+ *   "max_generations" 1..65536: the most generations one session of this
+ *                 handle may run (65536); the workspace holds one statistics
+ *                 record (80 bytes) per generation, so a smaller value
+ *                 shrinks plse_workspace_bytes.  plse_solve / plse_step
+ *                 beyond it return PLSE_E_ARG.  The server sets it to each
+ *                 request's generation budget while the request is held and
+ *                 restores the caller's value when it ends.
  * Errors: PLSE_E_PARAM.
  */
 /* Test hook (selection): "select_global_sort" 1 sorts the selection keys with
@@ -364,9 +371,12 @@ int plse_server_poll(plse_server s, uint64_t ticket, int8_t *best_grid, int32_t 
                      plse_timing *timing);
 /* Requests waiting, resident, and finished but not yet polled. */
 /* plse_server_cancel: a waiting request is dropped (poll: PLSE_E_CANCELLED, no
- * grid); a resident one stops at the end of its current generation and its
- * poll returns PLSE_E_CANCELLED with the best grid found so far (filled and
- * timing set).  PLSE_E_ARG for an unknown or already finished ticket. */
+ * grid); a resident one stops once the generations already enqueued on its
+ * stream have run (at most two beyond the current one), and its poll returns
+ * PLSE_E_CANCELLED with the best grid found by then (filled and timing set;
+ * generations and time to best include those drained generations, whose end
+ * times come from their end events).  PLSE_E_ARG for an unknown or already
+ * finished ticket. */
 int plse_server_cancel(plse_server s, uint64_t ticket);
 int plse_server_status(plse_server s, int32_t *waiting, int32_t *resident, int32_t *finished);
 int plse_server_destroy(plse_server s);

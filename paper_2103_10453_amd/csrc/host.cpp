@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/plse.h"
+#include "host_books.h"
 #include "kernels.h"
 
 using namespace plse;
@@ -98,6 +99,7 @@ struct plse_instance {
     int spl = 0;  // candidate positions per lane and round in PLITS; 0: automatic
     int wpb = 0;  // waves per block in PLITS; 0: automatic
     int fail_at = 0;  // serving test hook: end the request after this generation
+    int max_gens = PLSE_MAX_GENERATIONS;  // generations a session may run (sizes its records)
     int sel_global = 0;  // test hook: sort selection keys in global memory when possible
 
     uint8_t *ws = nullptr;
@@ -252,7 +254,7 @@ Layout plan(const plse_instance *h, int p) {
     L.nbr = take(4 * nv * (size_t)std::max(h->nl, 1));
     L.args = take(sizeof(ArgBlock));
     L.ctl = take(sizeof(Ctl));
-    L.stats = take(sizeof(GenStat) * PLSE_MAX_GENERATIONS);
+    L.stats = take(sizeof(GenStat) * (size_t)h->max_gens);
     L.Sstar = take(st);
     L.S_all = take(m * st);
     L.S_off = take((size_t)p * st);
@@ -731,7 +733,8 @@ int session_begin(Session &S, const uint64_t *seeds, hipStream_t s) {
 }
 
 int session_step(Session &S, int generations, hipStream_t s) {
-    if (S.base + S.steps + generations > PLSE_MAX_GENERATIONS) return PLSE_E_ARG;
+    for (const plse_instance *h : S.hs)
+        if (S.base + S.steps + generations > h->max_gens) return PLSE_E_ARG;
     while (S.ev.size() < 3 * (size_t)(S.steps + generations)) {
         hipEvent_t e = nullptr;
         HIP_TRY(hipEventCreate(&e));
@@ -793,36 +796,14 @@ int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &o
     for (size_t i = 0; i < S.hs.size(); ++i) {
         plse_instance *h = S.hs[i];
         const int gens = std::min(ctl[i].gens_run, G);  // every stepped generation has ended
-        h->gen_best.assign((size_t)gens, 0);
-        h->gen_cnt.assign((size_t)gens * kCounters, 0);
-        plse_stats &ls = h->last;
-        std::memset(&ls, 0, sizeof(ls));
-        for (int g = 0; g < gens; ++g) {
-            h->gen_best[g] = gs[i][g].best_f;
-            for (int q = 0; q < kCounters; ++q) {
-                h->gen_cnt[(size_t)g * kCounters + q] = gs[i][g].cnt[q];
-                ls.totals[q] += gs[i][g].cnt[q];
-            }
-        }
-        ls.generations_run = gens;
-        ls.best_f = ctl[i].fstar;
-        ls.best_generation = ctl[i].best_gen;
-        ls.stop_reason = ctl[i].stop_reason;
+        RunResult rr = summarize(ctl[i], gs[i].data(), gens);
+        h->last = rr.stats;
+        h->gen_best = std::move(rr.gen_best);
+        h->gen_cnt = std::move(rr.gen_cnt);
         h->ms_plits = tp;
         h->ms_rest = tr;
-        // best grid: prefilled cells plus S* on the vertices
         const size_t slot = (size_t)(std::find(order.begin(), order.end(), h) - order.begin());
-        int8_t *out = grids[slot];
-        const int n = h->n;
-        int cnt = 0;
-        for (int c = 0; c < n * n; ++c) {
-            const int v = h->cell_v[c];
-            const int8_t val =
-                (v == -1) ? h->grid[c] : ((v >= 0 && gens > 0) ? (int8_t)star[i][v] : (int8_t)0);
-            out[c] = val;
-            cnt += (val != 0);
-        }
-        filled[slot] = cnt;
+        filled[slot] = best_grid(h->n, h->cell_v, h->grid, star[i].data(), gens, grids[slot]);
     }
     return PLSE_OK;
 }
@@ -1059,6 +1040,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "fail_at_generation") {
         if (v < 0 || v > PLSE_MAX_GENERATIONS) return PLSE_E_PARAM;
         h->fail_at = (int)v;
+    } else if (k == "max_generations") {
+        if (v < 1 || v > PLSE_MAX_GENERATIONS) return PLSE_E_PARAM;
+        h->max_gens = (int)v;
     } else {
         return PLSE_E_PARAM;
     }
@@ -1086,6 +1070,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "slots_per_lane") *v = choose_spl(h);
     else if (k == "waves_per_block") *v = choose_wpb(h);
     else if (k == "fail_at_generation") *v = h->fail_at;
+    else if (k == "max_generations") *v = h->max_gens;
     else if (k == "select_global_sort") *v = h->sel_global;
     else return PLSE_E_PARAM;
     return PLSE_OK;
@@ -1253,7 +1238,7 @@ int plse_resume(plse_handle h, int32_t p, void *stream, const void *buf, size_t 
     std::memcpy(&hd, buf, sizeof(hd));
     if (hd.magic != kCkptMagic || hd.version != kCkptVersion || hd.n != h->n || hd.nv != h->nv ||
         hd.stride != h->stride || hd.p != p || hd.ident != run_ident(h) || hd.gens_run < 0 ||
-        hd.gens_run > PLSE_MAX_GENERATIONS)
+        hd.gens_run > h->max_gens)
         return PLSE_E_ARG;
     BusyGuard guard(h);
     if (!guard.ok) return PLSE_E_BUSY;
@@ -1294,7 +1279,7 @@ int plse_resume(plse_handle h, int32_t p, void *stream, const void *buf, size_t 
 
 int plse_solve(plse_handle h, int32_t p, int32_t G, uint64_t seed, void *stream,
                int8_t *best_grid, int32_t *filled) {
-    if (!h || !best_grid || !filled || G < 1 || G > PLSE_MAX_GENERATIONS) return PLSE_E_ARG;
+    if (!h || !best_grid || !filled || G < 1 || G > h->max_gens) return PLSE_E_ARG;
     int rc = plse_begin(h, p, seed, stream);
     if (rc) return rc;
     rc = plse_step(h, G, stream);
@@ -1314,7 +1299,7 @@ int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t p, int32_t G,
         G > PLSE_MAX_GENERATIONS)
         return PLSE_E_ARG;
     for (int i = 0; i < count; ++i) {
-        if (!hs[i] || !best_grids[i]) return PLSE_E_ARG;
+        if (!hs[i] || !best_grids[i] || G > hs[i]->max_gens) return PLSE_E_ARG;
         for (int j = 0; j < i; ++j)
             if (hs[j] == hs[i]) return PLSE_E_ARG;
     }
@@ -1585,17 +1570,20 @@ struct Request {
     int filled = 0, best_gen = 0;
     uint64_t moves = 0;
     std::atomic<bool> cancel{false};  // plse_server_cancel on a resident request
+    int caller_max_gens = 0;  // the handle's own setting, restored when the request ends
 };
 
-// Results of one finished request (the stream is idle).
+// Results of one finished request (its stream has drained).  The
+// statistics cover the generations the device ran, which can exceed those
+// the worker saw end (generations still queued at a cancel or a stop): their
+// end times come from their end events, relative to the last generation the
+// worker saw end (or to the first search's start event).
 int collect(Request &r, hipStream_t s) {
     plse_instance *h = r.h;
     Ctl c{};
-    // the control block first: generations may have run beyond the last one
-    // the worker saw end (a request cancelled with generations queued)
     HIP_TRY(hipMemcpyAsync(&c, at<Ctl>(h, h->L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (c.gens_run < 0 || c.gens_run > PLSE_MAX_GENERATIONS) return PLSE_E_HIP;
+    if (c.gens_run < 0 || c.gens_run > h->max_gens) return PLSE_E_HIP;
     std::vector<GenStat> gs((size_t)std::max(c.gens_run, 1));
     std::vector<uint8_t> star((size_t)h->stride);
     HIP_TRY(hipMemcpyAsync(gs.data(), at<GenStat>(h, h->L.stats), sizeof(GenStat) * gs.size(),
@@ -1604,34 +1592,26 @@ int collect(Request &r, hipStream_t s) {
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const int gens = c.gens_run;
-    h->gen_best.assign((size_t)gens, 0);
-    h->gen_cnt.assign((size_t)gens * kCounters, 0);
-    std::memset(&h->last, 0, sizeof(h->last));
-    for (int g = 0; g < gens; ++g) {
-        h->gen_best[g] = gs[g].best_f;
-        for (int q = 0; q < kCounters; ++q) {
-            h->gen_cnt[(size_t)g * kCounters + q] = gs[g].cnt[q];
-            h->last.totals[q] += gs[g].cnt[q];
-        }
-    }
-    h->last.generations_run = gens;
-    h->last.best_f = c.fstar;
-    h->last.best_generation = c.best_gen;
-    h->last.stop_reason = c.stop_reason;
+    RunResult rr = summarize(c, gs.data(), gens);
+    h->last = rr.stats;
+    h->gen_best = std::move(rr.gen_best);
+    h->gen_cnt = std::move(rr.gen_cnt);
     r.best_gen = c.best_gen;
     r.moves = h->last.totals[C_MOVES];
     r.steps = std::max(r.steps, gens);  // generations run, seen ending or not
-    const int n = h->n;
-    r.grid.assign((size_t)n * n, 0);
-    int cnt = 0;
-    for (int q = 0; q < n * n; ++q) {
-        const int v = h->cell_v[q];
-        const int8_t val =
-            (v == -1) ? h->grid[q] : ((v >= 0 && gens > 0) ? (int8_t)star[v] : (int8_t)0);
-        r.grid[q] = val;
-        cnt += (val != 0);
+    if (r.S && (int)r.t_gen.size() < gens && (size_t)3 * gens <= r.S->ev.size()) {
+        const size_t k = r.t_gen.size();
+        const hipEvent_t ref = k ? r.S->ev[3 * (k - 1) + 2] : r.S->ev[0];
+        const double base = k ? r.t_gen.back() : r.t_admit;
+        for (int g = (int)k; g < gens; ++g) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ref, r.S->ev[3 * (size_t)g + 2]) != hipSuccess) break;
+            r.t_gen.push_back(base + 1e-3 * ms);
+        }
+        (void)hipGetLastError();
     }
-    r.filled = cnt;
+    r.grid.assign((size_t)h->n * h->n, 0);
+    r.filled = best_grid(h->n, h->cell_v, h->grid, star.data(), gens, r.grid.data());
     return PLSE_OK;
 }
 
@@ -1653,7 +1633,7 @@ struct plse_server_s {
     std::map<uint64_t, Request *> finished;
     std::set<uint64_t> live;  // submitted and not yet finished (waiting, admitting, resident)
     std::set<uint64_t> cancelled;  // cancel requests for tickets being admitted
-    std::map<size_t, size_t> free_blocks;  // offset -> bytes
+    FirstFitArena blocks{0, kAlign};  // the arena's free blocks
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread worker;
@@ -1663,35 +1643,8 @@ struct plse_server_s {
     }
 
     // First-fit placement in the arena (256-byte granules); merge on release.
-    bool place(Request *r) {
-        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
-            if (it->second >= r->bytes) {
-                r->off = it->first;
-                const size_t rest = it->second - r->bytes;
-                const size_t at2 = it->first + r->bytes;
-                free_blocks.erase(it);
-                if (rest) free_blocks[at2] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-
-    void release(Request *r) {
-        auto it = free_blocks.emplace(r->off, r->bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_blocks.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_blocks.erase(nx);
-        }
-        if (it != free_blocks.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_blocks.erase(it);
-            }
-        }
-    }
+    bool place(Request *r) { return blocks.place(r->bytes, &r->off); }
+    void release(Request *r) { blocks.release(r->off, r->bytes); }
 
     void finish(Request *r, int status) {
         cancelled.erase(r->ticket);
@@ -1699,6 +1652,7 @@ struct plse_server_s {
         r->t_done = now();
         r->h->ws = nullptr;
         r->h->ws_bytes = 0;
+        r->h->max_gens = r->caller_max_gens;
         r->h->in_session = false;
         release(r);
         live.erase(r->ticket);
@@ -1852,7 +1806,7 @@ int plse_server_create(size_t budget, void *device_ptr, int32_t max_slots, void 
     s->stream = reinterpret_cast<hipStream_t>(stream);
     (void)hipGetDevice(&s->device);
     s->t0 = std::chrono::steady_clock::now();
-    s->free_blocks[0] = s->budget;
+    s->blocks = FirstFitArena(s->budget, kAlign);
     set_attributes_once();
     hipError_t e = hipEventCreateWithFlags(&s->ready, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(s->ready, s->stream);
@@ -1878,8 +1832,12 @@ int plse_server_submit(plse_server s, plse_handle h, int32_t p, int32_t G, uint6
     r->p = p;
     r->G = G;
     r->seed = seed;
+    // the request's statistics records are sized by its generation budget
+    r->caller_max_gens = h->max_gens;
+    h->max_gens = G;
     r->bytes = round_up(plan(h, p).total, kAlign);
     if (r->bytes > s->budget) {
+        h->max_gens = r->caller_max_gens;
         delete r;
         return PLSE_E_CAPACITY;
     }
@@ -1911,9 +1869,7 @@ int plse_server_poll(plse_server s, uint64_t ticket, int8_t *best_grid, int32_t 
         t->submit_s = r->t_submit;
         t->admit_s = r->t_admit;
         t->done_s = r->t_done;
-        t->best_s = (r->best_gen >= 1 && r->best_gen <= (int)r->t_gen.size())
-                        ? r->t_gen[r->best_gen - 1]
-                        : r->t_done;
+        t->best_s = time_to_best(r->t_gen, r->steps, r->best_gen, r->t_done);
         t->generations = r->steps;
         t->best_generation = r->best_gen;
         t->filled = r->filled;
@@ -1936,6 +1892,7 @@ int plse_server_cancel(plse_server s, uint64_t ticket) {
         s->waiting.erase(it);
         r->status = PLSE_E_CANCELLED;
         r->t_done = s->now();
+        r->h->max_gens = r->caller_max_gens;
         r->h->in_session = false;
         s->live.erase(ticket);
         s->finished[ticket] = r;
@@ -1970,11 +1927,13 @@ int plse_server_destroy(plse_server s) {
     }
     if (s->worker.joinable()) s->worker.join();
     for (Request *r : s->waiting) {
+        r->h->max_gens = r->caller_max_gens;
         r->h->in_session = false;
         delete r;
     }
     for (Request *r : s->resident) {
         s->retire(r);
+        r->h->max_gens = r->caller_max_gens;
         r->h->in_session = false;
         r->h->ws = nullptr;
         delete r;

@@ -1,7 +1,6 @@
 // plse_internal.h -- structures shared by the host orchestrator and the HIP
 // kernels of libplse (gfx950).  Plain data only.
 #pragma once
-#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
