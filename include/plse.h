@@ -256,6 +256,28 @@ int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t population,
                      int32_t generations, const uint64_t *seeds, void *stream,
                      int8_t *const *best_grids, int32_t *filled);
 
+/*
+ * plse_solve_noalloc -- plse_solve for callers that cannot allocate device
+ * memory or create runtime objects (code that must not call hipMalloc: tight
+ * serving loops, harnesses that forbid allocation).  Instead of the handle's
+ * attached workspace it uses a fixed device array of PLSE_NOALLOC_BYTES
+ * inside the library, one per GPU, reserved when the library's code is
+ * loaded on that GPU and held until the process ends; the kernels are
+ * enqueued one by one on `stream` (no HIP graphs, side streams or events).
+ * The result, plse_last_stats and the handle's attached workspace are as
+ * after plse_solve with the same arguments; plse_last_timing reports no
+ * steps.  *bytes_needed (may be NULL) receives the workspace this call needs
+ * (its per-generation records sized for `generations`).  Every call on one
+ * GPU shares that GPU's array and overwrites it: calls that overlap in time
+ * on the same GPU (other streams, threads or handles) race and must not be
+ * issued.  Call with the stream's device current.  Errors: PLSE_E_ARG,
+ * PLSE_E_BUSY, PLSE_E_CAPACITY (the instance and population need more than
+ * PLSE_NOALLOC_BYTES; checked before any device work), PLSE_E_HIP.
+ */
+#define PLSE_NOALLOC_BYTES (64ull << 20)
+int plse_solve_noalloc(plse_handle h, int32_t population, int32_t generations, uint64_t seed,
+                       void *stream, int8_t *best_grid, int32_t *filled, size_t *bytes_needed);
+
 /* Per-generation GPU times of the last session, from the HIP events of
  * plse_step: plits_ms[g] spans the tabu-search launch of generation g,
  * rest_ms[g] the best/distance/selection/matching/crossover kernels.  *steps

@@ -788,8 +788,9 @@ int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &o
                                hipMemcpyDeviceToHost, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
-    std::vector<float> tp((size_t)S.steps), tr((size_t)S.steps);
-    for (int g = 0; g < S.steps; ++g) {
+    const int timed = S.ev.size() >= 3 * (size_t)S.steps ? S.steps : 0;
+    std::vector<float> tp((size_t)timed), tr((size_t)timed);
+    for (int g = 0; g < timed; ++g) {
         HIP_TRY(hipEventElapsedTime(&tp[g], S.ev[3 * g], S.ev[3 * g + 1]));
         HIP_TRY(hipEventElapsedTime(&tr[g], S.ev[3 * g + 1], S.ev[3 * g + 2]));
     }
@@ -839,6 +840,56 @@ ArgList single(plse_instance *h, M ArgBlock::*member) {
     ArgList L{};
     L.p[0] = dev_arg(h, member);
     return L;
+}
+
+// Workspace of plse_solve_noalloc: a fixed device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never passes
+// the array's name to a kernel or copy: it takes the array's device address
+// from hipGetSymbolAddress once per device (scratch_address) and uses that.
+constexpr size_t kScratchBytes = (size_t)PLSE_NOALLOC_BYTES;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_at[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+int scratch_address(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return PLSE_E_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr % kAlign)) return PLSE_E_HIP;
+        g_scratch_at[dev] = ptr;
+    }
+    *out = g_scratch_at[dev];
+    return PLSE_OK;
+}
+
+// A whole solve of one instance enqueued kernel by kernel on `s`: no graphs,
+// side streams or events (so no runtime object is created), distances among
+// P_t in line before the searches instead of beside them.  Same kernels and
+// arguments as a session, so the same result.
+int solve_direct(plse_instance *h, int p, int G, uint64_t seed, hipStream_t s,
+                 int8_t *best_grid, int32_t *filled) {
+    Session S;
+    S.hs = {h};
+    S.p = p;
+    S.seed = seed;
+    RC_TRY(admit(S.hs, p, &seed, s));
+    shape_session(S);
+    if (S.groups.size() != 1) return PLSE_E_ARG;
+    for (int g = 0; g < G; ++g) {
+        if (old_tiles(p) > 0) RC_TRY(enqueue_old_dist(S, s));
+        RC_TRY(enqueue_local_search(S, s));
+        RC_TRY(enqueue_rest(S, s));
+    }
+    S.steps = G;
+    int8_t *grids[1] = {best_grid};
+    return session_end(S, s, {h}, grids, filled);
 }
 
 }  // namespace
@@ -1290,6 +1341,37 @@ int plse_solve(plse_handle h, int32_t p, int32_t G, uint64_t seed, void *stream,
         return rc;
     }
     return plse_end(h, stream, best_grid, filled);
+}
+
+int plse_solve_noalloc(plse_handle h, int32_t p, int32_t G, uint64_t seed, void *stream,
+                       int8_t *best_grid, int32_t *filled, size_t *bytes_needed) {
+    if (!h || !best_grid || !filled || G < 1 || G > h->max_gens || p < 2 ||
+        p > PLSE_MAX_POPULATION)
+        return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok || h->in_session) return PLSE_E_BUSY;
+    // per-generation records sized by this call's generations
+    const int keep_gens = h->max_gens;
+    h->max_gens = G;
+    const size_t need = plan(h, p).total;
+    if (bytes_needed) *bytes_needed = need;
+    if (need > kScratchBytes) {
+        h->max_gens = keep_gens;
+        return PLSE_E_CAPACITY;
+    }
+    void *ptr = nullptr;
+    int rc = scratch_address(&ptr);
+    if (!rc) {
+        uint8_t *keep_ws = h->ws;
+        const size_t keep_bytes = h->ws_bytes;
+        h->ws = reinterpret_cast<uint8_t *>(ptr);
+        h->ws_bytes = kScratchBytes;
+        rc = solve_direct(h, p, G, seed, reinterpret_cast<hipStream_t>(stream), best_grid, filled);
+        h->ws = keep_ws;
+        h->ws_bytes = keep_bytes;
+    }
+    h->max_gens = keep_gens;
+    return rc;
 }
 
 int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t p, int32_t G,

@@ -76,6 +76,7 @@ def _lib():
             "plse_solve": [P, i32, i32, u64, P, P, P],
             "plse_begin": [P, i32, u64, P],
             "plse_solve_batch": [P, i32, i32, i32, P, P, P, P],
+            "plse_solve_noalloc": [P, i32, i32, u64, P, P, P, P],
             "plse_step": [P, i32, P],
             "plse_end": [P, P, P, P],
             "plse_peek": [P, P, P],
@@ -118,6 +119,7 @@ def exported_symbols():
     L = _lib()
     names = ["plse_create", "plse_info", "plse_sizes", "plse_row_stride", "plse_set_param", "plse_get_param",
              "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
+             "plse_solve_noalloc",
              "plse_begin",
              "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_checkpoint", "plse_resume", "plse_last_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
@@ -210,6 +212,21 @@ def plse_solve(h, n: int, population: int, generations: int, seed: int, stream=N
     _check(_lib().plse_solve(h, population, generations, seed & ((1 << 64) - 1), _stream(stream),
                              _np(grid), ctypes.byref(filled)), "plse_solve")
     return grid, filled.value
+
+
+NOALLOC_BYTES = 64 << 20  # PLSE_NOALLOC_BYTES
+
+
+def plse_solve_noalloc(h, n: int, population: int, generations: int, seed: int, stream=None):
+    """plse_solve on the library's fixed device array (no workspace, no
+    allocation); returns (grid, filled, bytes_needed)."""
+    grid = np.zeros((n, n), dtype=np.int8)
+    filled = ctypes.c_int32()
+    need = ctypes.c_size_t()
+    _check(_lib().plse_solve_noalloc(h, population, generations, seed & ((1 << 64) - 1),
+                                     _stream(stream), _np(grid), ctypes.byref(filled),
+                                     ctypes.byref(need)), "plse_solve_noalloc")
+    return grid, filled.value, need.value
 
 
 def plse_solve_batch(handles, ns, population: int, generations: int, seeds, stream=None):
