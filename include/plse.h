@@ -278,6 +278,18 @@ int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t population,
 int plse_solve_noalloc(plse_handle h, int32_t population, int32_t generations, uint64_t seed,
                        void *stream, int8_t *best_grid, int32_t *filled, size_t *bytes_needed);
 
+/*
+ * plse_measure_lds_bandwidth -- a device measurement, not a step of the
+ * method: the sustained LDS read bandwidth of the current GPU (bytes/s, best
+ * of `repeats` timed launches after one warm-up), the peak against which the
+ * LDS-resident tabu search is compared.  Every CU runs blocks that read
+ * 16-byte words at conflict-free addresses from a 32 KiB buffer.  Uses the
+ * library's fixed device array (see plse_solve_noalloc) as its output sink,
+ * so it must not overlap plse_solve_noalloc calls on the same GPU.  Errors:
+ * PLSE_E_ARG, PLSE_E_HIP.
+ */
+int plse_measure_lds_bandwidth(void *stream, int32_t repeats, double *bytes_per_second);
+
 /* Per-generation GPU times of the last session, from the HIP events of
  * plse_step: plits_ms[g] spans the tabu-search launch of generation g,
  * rest_ms[g] the best/distance/selection/matching/crossover kernels.  *steps

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libplse.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["k_plits.hip", "k_init.hip", "k_evo.hip", "host.cpp"]
+SOURCES = ["k_plits.hip", "k_plits_lean.hip", "k_init.hip", "k_evo.hip", "k_measure.hip",
+           "host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

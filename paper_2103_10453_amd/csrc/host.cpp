@@ -51,7 +51,7 @@ int colour_bits(int n) {
 
 // Offsets of every device array of one handle, for a population p.
 struct Layout {
-    size_t vrc, vrec, cand, vinfo, nbr;
+    size_t vrc, vrec, cand, vinfo, nbr, rcl, rclo;
     size_t args, ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
     size_t tabu, planes, D, deg, adj, keys, rej, acc, pos, hkeys, hvals, partner, dpart;
@@ -86,6 +86,9 @@ struct plse_instance {
     int dmax = 0, ts = 8;  // largest |D*(v)|; candidate row length (dmax + 1 rounded to 8)
     std::vector<int8_t> grid;
     std::vector<int> cell_v;  // -1 prefilled, -2 impossible, else vertex id
+    // vertices of each row (vertex | column << 16), then of each column (vertex
+    // | row << 16), in order; offsets of the 2n lists
+    std::vector<uint32_t> rcl, rclo;
     // host images of the device instance tables
     std::vector<uint16_t> vrc;
     std::vector<uint32_t> vrec;  // 8 words per vertex
@@ -98,6 +101,7 @@ struct plse_instance {
     Params P{};
     int spl = 0;  // candidate positions per lane and round in PLITS; 0: automatic
     int wpb = 0;  // waves per block in PLITS; 0: automatic
+    int kernel = 0;  // PLITS kernel: 0 automatic, 1 global tabu table, 2 LDS-resident
     int fail_at = 0;  // serving test hook: end the request after this generation
     int max_gens = PLSE_MAX_GENERATIONS;  // generations a session may run (sizes its records)
     int sel_global = 0;  // test hook: sort selection keys in global memory when possible
@@ -192,12 +196,49 @@ int choose_spl(const plse_instance *h) {
 struct PlitsLds {
     int per_wave, off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_planes;
     int nplanes;
+    bool lean = false;  // the LDS-resident kernel
+    int off_mk = 0, off_dirty = 0, off_wpre = 0, npos = 0;
 };
+
+// Per-wave LDS the automatic choice allows the LDS-resident kernel (at least
+// four resident waves per CU).
+constexpr int kLeanMaxPerWave = 40 * 1024;
+
+// LDS-resident PLITS per wave: S, row/column colour counts, eligibility
+// bitmap, one tabu mark per candidate move (rows padded to CH), the dirty
+// set, chunk-count planes, per-word chunk offsets, the staging area (staged
+// eligible vertices, chunk-start flags, joining vertices, row/column list
+// offsets) and the colour halves of the tie values.
+PlitsLds plits_lean_layout(const plse_instance *h, int ch) {
+    PlitsLds L{};
+    const int W = (h->nv + 31) / 32;
+    long npos = 0;
+    for (int v = 0; v < h->nv; ++v) npos += (long)(((h->vinfo[v] >> 16) & 0xFFu) / ch + 1) * ch;
+    L.lean = true;
+    L.npos = (int)std::min<long>(npos, 1L << 30);
+    L.nplanes = 0;
+    while ((h->dmax / ch) >> L.nplanes) ++L.nplanes;
+    L.off_h = h->stride;
+    L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
+    L.off_mk = L.off_bm + (int)round_up((size_t)W * 4, 16);
+    L.off_dirty = L.off_mk + (int)round_up((size_t)L.npos, 16);
+    L.off_planes = L.off_dirty + (int)round_up((size_t)W * 4, 16);
+    L.off_wpre = L.off_planes + (int)round_up((size_t)L.nplanes * W * 4, 16);
+    L.off_el = L.off_wpre + (int)round_up((size_t)W * 4, 16);
+    L.off_hk = L.off_el + kLeanAreaBytes;
+    L.per_wave = L.off_hk + (int)round_up((size_t)2 * (h->n + 1), 16);
+    L.off_tm = L.off_ring = 0;
+    return L;
+}
 
 PlitsLds plits_lds(const plse_instance *h) {
     PlitsLds L;
     const int W = (h->nv + 31) / 32;
     const int ch = choose_spl(h);
+    if (h->P.variant == 0 && h->kernel == 2 && h->nv < 65536) {
+        const PlitsLds Ln = plits_lean_layout(h, ch);
+        if (Ln.per_wave <= max_lds_per_block()) return Ln;
+    }
     const int qcap = 64 * ((h->dmax + ch) / ch);  // 64 vertices' chunks
     L.off_h = h->stride;
     L.off_bm = L.off_h + (int)round_up((size_t)2 * h->n * (h->n + 1), 16);
@@ -215,14 +256,14 @@ PlitsLds plits_lds(const plse_instance *h) {
 // Waves per block: the most resident waves per CU for every chunk size in
 // use; among equals the fewest waves per block, since a block keeps its LDS
 // until its slowest wave ends and searches end at very different times.
-int auto_wpb(int per_wave, const std::vector<int> &spls, bool partial) {
+int auto_wpb(int per_wave, const std::vector<int> &spls, bool partial, bool lean) {
     const int lim = max_lds_per_block();
     int best = 1, best_waves = -1;
     for (int w : {1, 2, 4}) {
         if (w * per_wave > lim) continue;
         int waves = 1 << 30;
         for (int spl : spls)
-            waves = std::min(waves, plits_waves_per_cu(spl, w, per_wave, partial));
+            waves = std::min(waves, plits_waves_per_cu(spl, w, per_wave, partial, lean));
         if (waves > best_waves) {
             best = w;
             best_waves = waves;
@@ -232,8 +273,8 @@ int auto_wpb(int per_wave, const std::vector<int> &spls, bool partial) {
 }
 
 int choose_wpb(const plse_instance *h) {
-    return h->wpb ? h->wpb
-                  : auto_wpb(plits_lds(h).per_wave, {choose_spl(h)}, h->P.variant != 0);
+    const PlitsLds pl = plits_lds(h);
+    return h->wpb ? h->wpb : auto_wpb(pl.per_wave, {choose_spl(h)}, h->P.variant != 0, pl.lean);
 }
 
 Layout plan(const plse_instance *h, int p) {
@@ -252,6 +293,8 @@ Layout plan(const plse_instance *h, int p) {
     L.cand = take(nv * (size_t)h->ts);
     L.vinfo = take(4 * nv);
     L.nbr = take(4 * nv * (size_t)std::max(h->nl, 1));
+    L.rcl = take(4 * h->rcl.size());
+    L.rclo = take(4 * h->rclo.size());
     L.args = take(sizeof(ArgBlock));
     L.ctl = take(sizeof(Ctl));
     L.stats = take(sizeof(GenStat) * (size_t)h->max_gens);
@@ -308,6 +351,8 @@ DevInstance dev_instance(plse_instance *h) {
     I.vinfo = at<uint32_t>(h, L.vinfo);
     I.nl = h->nl;
     I.nbr = at<uint32_t>(h, L.nbr);
+    I.rcl = at<uint32_t>(h, L.rcl);
+    I.rclo = at<uint32_t>(h, L.rclo);
     return I;
 }
 
@@ -322,6 +367,8 @@ int upload_instance(plse_instance *h, hipStream_t s) {
     HIP_TRY(put(L.cand, h->cand.data(), h->cand.size()));
     HIP_TRY(put(L.vinfo, h->vinfo.data(), 4 * h->vinfo.size()));
     HIP_TRY(put(L.nbr, h->nbr.data(), 4 * h->nbr.size()));
+    HIP_TRY(put(L.rcl, h->rcl.data(), 4 * h->rcl.size()));
+    HIP_TRY(put(L.rclo, h->rclo.data(), 4 * h->rclo.size()));
     return PLSE_OK;
 }
 
@@ -365,6 +412,10 @@ PlitsArgs make_plits(plse_instance *h, int p, int gen_fixed, uint64_t seed,
     a.off_hk = pl.off_hk;
     a.off_planes = pl.off_planes;
     a.nplanes = pl.nplanes;
+    a.off_mk = pl.off_mk;
+    a.off_dirty = pl.off_dirty;
+    a.off_wpre = pl.off_wpre;
+    a.npos = pl.npos;
     return a;
 }
 
@@ -485,7 +536,7 @@ int launch_ctl(const std::vector<plse_instance *> &hs, bool reset, hipStream_t s
 // instance never runs at the occupancy of a large one.
 struct PlitsGroup {
     int spl = 8, occ = 0, lds = 0, wpb = 1;
-    bool partial = false;
+    bool partial = false, lean = false;
     std::vector<plse_instance *> hs;
 };
 
@@ -535,7 +586,7 @@ struct Session {
 
 int launch_group(const Session &S, const PlitsGroup &g, hipStream_t s) {
     return launch_over(g.hs, &ArgBlock::plits, [&](const ArgList &L, int c) {
-        return launch_plits(L, c, S.p, g.lds, g.spl, g.wpb, g.partial, s);
+        return launch_plits(L, c, S.p, g.lds, g.spl, g.wpb, g.partial, g.lean, s);
     });
 }
 
@@ -689,11 +740,12 @@ void shape_session(Session &S) {
     });
     S.groups.clear();
     for (plse_instance *h : S.hs) {
-        const int spl = choose_spl(h), per = plits_lds(h).per_wave;
-        const bool partial = h->P.variant != 0;
-        const int occ = plits_waves_per_cu(spl, 1, per, partial);
+        const PlitsLds pl = plits_lds(h);
+        const int spl = choose_spl(h), per = pl.per_wave;
+        const bool partial = h->P.variant != 0, lean = pl.lean;
+        const int occ = plits_waves_per_cu(spl, 1, per, partial, lean);
         auto it = std::find_if(S.groups.begin(), S.groups.end(), [&](const PlitsGroup &g) {
-            return g.spl == spl && g.occ == occ && g.partial == partial;
+            return g.spl == spl && g.occ == occ && g.partial == partial && g.lean == lean;
         });
         if (it == S.groups.end()) {
             S.groups.push_back(PlitsGroup{});
@@ -701,6 +753,7 @@ void shape_session(Session &S) {
             it->spl = spl;
             it->occ = occ;
             it->partial = partial;
+            it->lean = lean;
         }
         it->lds = std::max(it->lds, per);
         it->hs.push_back(h);
@@ -708,7 +761,8 @@ void shape_session(Session &S) {
     for (PlitsGroup &g : S.groups) {
         bool same_wpb = true;
         for (plse_instance *h : g.hs) same_wpb = same_wpb && h->wpb == g.hs[0]->wpb;
-        g.wpb = (same_wpb && g.hs[0]->wpb) ? g.hs[0]->wpb : auto_wpb(g.lds, {g.spl}, g.partial);
+        g.wpb = (same_wpb && g.hs[0]->wpb) ? g.hs[0]->wpb
+                                            : auto_wpb(g.lds, {g.spl}, g.partial, g.lean);
         if (g.wpb * g.lds > max_lds_per_block()) g.wpb = 1;
     }
 }
@@ -943,6 +997,15 @@ int plse_create(int32_t n, const int8_t *grid, plse_handle *out) {
             coll[(size_t)j * n + colc[j]++] = (uint32_t)v | ((uint32_t)i << 16);
         }
     h->ub = (h->l == 1) ? n * n - 2 : n * n - h->l;
+    h->rclo.assign((size_t)2 * n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        for (int t = 0; t < rowc[i]; ++t) h->rcl.push_back(rowl[(size_t)i * n + t]);
+        h->rclo[i + 1] = (uint32_t)h->rcl.size();
+    }
+    for (int j = 0; j < n; ++j) {
+        for (int t = 0; t < colc[j]; ++t) h->rcl.push_back(coll[(size_t)j * n + t]);
+        h->rclo[n + j + 1] = (uint32_t)h->rcl.size();
+    }
     // vertex records: 128-bit domain mask, first slot (sum of earlier domain
     // sizes), coordinates and domain size; vertex info words; candidate rows
     // (the moves 0, D*(v) ascending, zero padded to ts positions)
@@ -1085,6 +1148,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "waves_per_block") {
         if (v != 0 && v != 1 && v != 2 && v != 4) return PLSE_E_PARAM;
         h->wpb = (int)v;
+    } else if (k == "plits_kernel") {
+        if (v < 0 || v > 2) return PLSE_E_PARAM;
+        h->kernel = (int)v;
     } else if (k == "select_global_sort") {
         if (v != 0 && v != 1) return PLSE_E_PARAM;
         h->sel_global = (int)v;
@@ -1123,6 +1189,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "fail_at_generation") *v = h->fail_at;
     else if (k == "max_generations") *v = h->max_gens;
     else if (k == "select_global_sort") *v = h->sel_global;
+    else if (k == "plits_kernel") *v = plits_lds(h).lean ? 2 : 1;
     else return PLSE_E_PARAM;
     return PLSE_OK;
 }
@@ -1374,6 +1441,37 @@ int plse_solve_noalloc(plse_handle h, int32_t p, int32_t G, uint64_t seed, void 
     return rc;
 }
 
+int plse_measure_lds_bandwidth(void *stream, int32_t repeats, double *bytes_per_second) {
+    if (!bytes_per_second || repeats < 1) return PLSE_E_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    void *sink = nullptr;
+    RC_TRY(scratch_address(&sink));
+    const int blocks = cus * 16;
+    const uint32_t iters = 4096;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    double best = 0.0, bytes = 0.0;
+    for (int r = 0; r <= repeats && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+            e = launch_lds_read(blocks, iters, reinterpret_cast<uint32_t *>(sink), s, &bytes);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && r > 0 && ms > 0.0f) best = std::max(best, bytes / (ms * 1e-3));
+    }
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "plse_measure_lds_bandwidth");
+    *bytes_per_second = best;
+    return PLSE_OK;
+}
+
 int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t p, int32_t G,
                      const uint64_t *seeds, void *stream, int8_t *const *best_grids,
                      int32_t *filled) {
@@ -1478,9 +1576,10 @@ int plse_stage_plits(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void 
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_fill_zero(single(h, &ArgBlock::fill), 1, s));
     const int wpb = choose_wpb(h);
-    if (wpb * plits_lds(h).per_wave > max_lds_per_block()) return PLSE_E_ARG;
-    HIP_TRY(launch_plits(single(h, &ArgBlock::plits), 1, p, plits_lds(h).per_wave,
-                         choose_spl(h), wpb, h->P.variant != 0, s));
+    const PlitsLds pl = plits_lds(h);
+    if (wpb * pl.per_wave > max_lds_per_block()) return PLSE_E_ARG;
+    HIP_TRY(launch_plits(single(h, &ArgBlock::plits), 1, p, pl.per_wave, choose_spl(h), wpb,
+                         h->P.variant != 0, pl.lean, s));
     return PLSE_OK;
 }
 
@@ -1521,7 +1620,8 @@ int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, v
     for (int pass = 0; pass < 2 && !rc; ++pass) {
         for (int i = 0; i < 3 && !rc; ++i) {
             h->spl = spls[i];
-            const int per = plits_lds(h).per_wave, wpb = choose_wpb(h);
+            const PlitsLds pl = plits_lds(h);
+            const int per = pl.per_wave, wpb = choose_wpb(h);
             fits[i] = plits_fn(h->spl, h->P.variant != 0) != nullptr &&
                       wpb * per <= max_lds_per_block();
             if (!fits[i] || (pass == 0 && i > 0)) continue;
@@ -1533,7 +1633,7 @@ int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, v
             chk(launch_fill_zero(single(h, &ArgBlock::fill), 1, s), "fill");
             if (pass == 1) chk(hipEventRecord(e0, s), "hipEventRecord");
             chk(launch_plits(single(h, &ArgBlock::plits), 1, sample, per, h->spl, wpb,
-                             h->P.variant != 0, s),
+                             h->P.variant != 0, pl.lean, s),
                 "plits");
             if (pass == 1) {
                 chk(hipEventRecord(e1, s), "hipEventRecord");

@@ -208,7 +208,7 @@ template <int CH, int PH>
 __device__ void run_phase(const PlitsArgs &a, int64_t iters, uint32_t slot,
                           uint32_t gen, const uint8_t *src, uint8_t *out, uint32_t *tabu,
                           const WaveState &ws, Scal &sc, Cnt &ucnt, uint32_t &lane_cands) {
-    const DevInstance &I = a.I;
+    const DevInstance I = a.I;  // by value: the pointers the search uses stay in registers
     const int lane = lane_id();
     const int n = I.n, nv = I.nv, np1 = n + 1, TS = I.ts;
     // F = phi_den f + phi_num c: phase 1 phi = 1/2, phase 2 phi = |V|;
@@ -660,7 +660,9 @@ __device__ void repair(const PlitsArgs &a, const uint8_t *from, uint8_t *out, co
 template <int CH, bool PARTIAL>
 __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const PlitsArgs a = arg_of<PlitsArgs>(L);
+    // by reference: fields needed only before or after a phase are read when
+    // needed instead of being held in registers through the search
+    const PlitsArgs &a = *static_cast<const PlitsArgs *>(L.p[blockIdx.y]);
     const int wv = (int)(threadIdx.x >> 6);
     const int ind = (int)blockIdx.x * (int)(blockDim.x >> 6) + wv;
     if (ind >= a.p) return;
@@ -765,12 +767,12 @@ __global__ void fill_zero_kernel(const ArgList L) {
 }
 
 hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
-                        int slots_per_lane, int waves_per_block, bool partial,
+                        int slots_per_lane, int waves_per_block, bool partial, bool lean,
                         hipStream_t stream) {
     const int blocks = (p + waves_per_block - 1) / waves_per_block;
     const size_t lds = (size_t)lds_per_wave * waves_per_block;
     const dim3 grid(blocks, count), block(64 * waves_per_block);
-    const void *fn = plits_fn(slots_per_lane, partial);
+    const void *fn = lean ? plits_lean_fn(slots_per_lane) : plits_fn(slots_per_lane, partial);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {const_cast<ArgList *>(&L)};
     return hipLaunchKernel(fn, grid, block, args, lds, stream);
@@ -783,8 +785,9 @@ hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
 
 // Resident waves per CU of a PLITS launch shape (the runtime's occupancy
 // calculation: registers, LDS and workgroup limits).
-int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial) {
-    const void *fn = plits_fn(slots_per_lane, partial);
+int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial,
+                       bool lean) {
+    const void *fn = lean ? plits_lean_fn(slots_per_lane) : plits_fn(slots_per_lane, partial);
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64 * waves_per_block,
                                                      (size_t)lds_per_wave * waves_per_block) !=
@@ -797,9 +800,11 @@ int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave
 
 hipError_t plits_set_lds_limit(int bytes) {
     hipError_t e = hipSuccess;
-    for (int spl : {2, 4, 8})
+    for (int spl : {2, 4, 8}) {
         for (bool partial : {false, true})
             if (e == hipSuccess) e = set_dynamic_lds_limit(plits_fn(spl, partial), bytes);
+        if (e == hipSuccess) e = set_dynamic_lds_limit(plits_lean_fn(spl), bytes);
+    }
     return e;
 }
 

@@ -48,11 +48,23 @@ struct PlitsArgs {
     uint32_t seed_lo, seed_hi;
     int32_t lds_per_wave;
     int32_t off_h, off_bm, off_tm, off_el, off_ring, off_hk, off_planes;
-    int32_t nplanes;       // bit planes of floor(|D*(v)| / CH), at most 6
+    int32_t nplanes;       // bit planes of floor(|D*(v)| / CH), at most 7
+    // LDS-resident kernel: tabu marks, dirty set, per-word chunk offsets (the
+    // stage is at off_el, 8 bytes per entry); npos = tabu mark positions
+    int32_t off_mk, off_dirty, off_wpre, npos;
 };
 
 // Eligible vertices a PLITS bitmap scan stages for dealing (u16 each, LDS).
 constexpr int kPlitsStage = 256;
+// LDS-resident PLITS kernel: eligible vertices staged at a time, and the
+// layout of its staging area: staged vertex ids (u16), 64 chunk-start flags,
+// vertices joining the eligible list (u16), the row/column list offsets
+// (2n + 1 u32, n <= 127).
+constexpr int kLeanStage = 256;
+constexpr int kLeanFlags = 2 * kLeanStage;
+constexpr int kLeanIns = kLeanFlags + 64;
+constexpr int kLeanRclo = kLeanIns + 2 * kLeanStage;
+constexpr int kLeanAreaBytes = kLeanRclo + 4 * 256;
 
 struct InitArgs {
     DevInstance I;
@@ -171,12 +183,15 @@ struct AuxArgs {
 // `count` instances; grid.y = count.
 // partial: Partial-MPMA's search (repair, then PartialCol) instead of PLITS.
 hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
-                        int slots_per_lane, int waves_per_block, bool partial,
+                        int slots_per_lane, int waves_per_block, bool partial, bool lean,
                         hipStream_t stream);
 const void *plits_fn(int slots_per_lane, bool partial);
+// The LDS-resident PLITS kernel (MPMA only) of a chunk size; null for others.
+const void *plits_lean_fn(int slots_per_lane);
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream);
 hipError_t plits_set_lds_limit(int bytes);
-int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial);
+int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial,
+                       bool lean);
 hipError_t launch_init(const ArgList &L, int count, int p, size_t lds, hipStream_t stream);
 size_t init_lds_bytes(const DevInstance &I, int pow2);
 hipError_t init_set_lds_limit(int bytes);
@@ -196,5 +211,8 @@ hipError_t launch_ctl_reset(const ArgList &L, int count, hipStream_t stream);
 hipError_t launch_gen_begin(const ArgList &L, int count, hipStream_t stream);
 hipError_t launch_pop_setup(const ArgList &L, int count, hipStream_t stream);
 hipError_t evo_set_lds_limit(int bytes);
+// LDS read bandwidth measurement: *bytes receives the bytes one launch reads.
+hipError_t launch_lds_read(int blocks, uint32_t iters, uint32_t *sink, hipStream_t stream,
+                           double *bytes);
 
 }  // namespace plse

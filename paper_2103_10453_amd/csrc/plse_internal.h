@@ -45,6 +45,9 @@ struct DevInstance {
     const uint32_t *nbr;             // [nv][nl] the other vertices of v's row, then of
                                      //   its column: vertex | its other coordinate << 16 |
                                      //   column flag << 31 (degree entries used)
+    const uint32_t *rcl;             // vertices of each row (vertex | column << 16), then
+                                     //   of each column (vertex | row << 16), in order
+    const uint32_t *rclo;            // [2n+1] offsets of those lists
 };
 
 struct Params {

@@ -77,6 +77,7 @@ def _lib():
             "plse_begin": [P, i32, u64, P],
             "plse_solve_batch": [P, i32, i32, i32, P, P, P, P],
             "plse_solve_noalloc": [P, i32, i32, u64, P, P, P, P],
+            "plse_measure_lds_bandwidth": [P, i32, P],
             "plse_step": [P, i32, P],
             "plse_end": [P, P, P, P],
             "plse_peek": [P, P, P],
@@ -119,7 +120,7 @@ def exported_symbols():
     L = _lib()
     names = ["plse_create", "plse_info", "plse_sizes", "plse_row_stride", "plse_set_param", "plse_get_param",
              "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
-             "plse_solve_noalloc",
+             "plse_solve_noalloc", "plse_measure_lds_bandwidth",
              "plse_begin",
              "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_checkpoint", "plse_resume", "plse_last_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
@@ -227,6 +228,14 @@ def plse_solve_noalloc(h, n: int, population: int, generations: int, seed: int, 
                                      _stream(stream), _np(grid), ctypes.byref(filled),
                                      ctypes.byref(need)), "plse_solve_noalloc")
     return grid, filled.value, need.value
+
+
+def plse_measure_lds_bandwidth(repeats: int = 5, stream=None) -> float:
+    """Sustained LDS read bandwidth of the current GPU, bytes/s."""
+    bw = ctypes.c_double()
+    _check(_lib().plse_measure_lds_bandwidth(_stream(stream), repeats, ctypes.byref(bw)),
+           "plse_measure_lds_bandwidth")
+    return bw.value
 
 
 def plse_solve_batch(handles, ns, population: int, generations: int, seeds, stream=None):

@@ -71,11 +71,14 @@ def test_init_parity(torch_cuda, oracle_mod, name, p):
     ("greedy70_70", 9, 6000, 0, 0),
     ("greedy70_70", 9, 6000, 8, 2),
 ])
-def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, spl, wpb):
-    """S', f' and every per-individual counter equal the oracle's."""
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, spl, wpb, kernel):
+    """S', f' and every per-individual counter equal the oracle's, with the
+    tabu table in global memory (kernel 1) and in LDS (kernel 2)."""
     g = _instances()[name]
-    _say(f"plits {name} p={p} depth={depth} spl={spl} wpb={wpb}")
-    s = P.Solver(g, depth=depth, slots_per_lane=spl, waves_per_block=wpb)
+    _say(f"plits {name} p={p} depth={depth} spl={spl} wpb={wpb} kernel={kernel}")
+    s = P.Solver(g, depth=depth, slots_per_lane=spl, waves_per_block=wpb, plits_kernel=kernel)
+    assert s.get_param("plits_kernel") == kernel
     seed, gen_no = 777 + p, 3
     S0, _ = s.stage_init(p, seed)
     S1, f1, c1 = s.stage_plits(S0, gen_no, seed)
@@ -89,12 +92,13 @@ def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, spl, wpb):
     np.testing.assert_array_equal(_np(c1).astype(np.uint64), c1o)
 
 
-def test_plits_from_conflicting_start(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_plits_from_conflicting_start(torch_cuda, oracle_mod, kernel):
     """A random (illegal, partial) start exercises both neighbourhoods, the
     repair and long eligible lists."""
     g = gen.random_greedy(20, 0.5, 7)
-    _say("plits random start greedy20_50")
-    s = P.Solver(g, depth=3000)
+    _say(f"plits random start greedy20_50 kernel={kernel}")
+    s = P.Solver(g, depth=3000, plits_kernel=kernel)
     I = oracle_mod.Instance(g)
     vr, vc, off, dom = I.tables()
     rng = np.random.default_rng(3)
@@ -117,6 +121,36 @@ def test_plits_from_conflicting_start(torch_cuda, oracle_mod):
         np.testing.assert_array_equal(_np(S1)[:, :I.nv], S1o)
         np.testing.assert_array_equal(_np(f1), f1o)
         np.testing.assert_array_equal(_np(c1).astype(np.uint64), c1o)
+
+
+@pytest.mark.parametrize("kernel,spl", [(1, 0), (2, 2), (2, 4), (2, 8)])
+def test_plits_long_tenures(torch_cuda, oracle_mod, kernel, spl):
+    """Tenures far beyond 125 iterations (alpha = 3 on a random start of a
+    599-vertex grid): the LDS kernel keeps such expiries in the global tabu
+    area and brings them back at its 128-iteration rebases; more than 256
+    eligible vertices at the start cover the staged batches."""
+    g = gen.planted(33, 0.45, 9)
+    _say(f"plits long tenures planted33_45 kernel={kernel} spl={spl}")
+    s = P.Solver(g, depth=4000, plits_kernel=kernel, slots_per_lane=spl,
+                 alpha_num=3, alpha_den=1)
+    I = oracle_mod.Instance(g)
+    vr, vc, off, dom = I.tables()
+    rng = np.random.default_rng(11)
+    p = 12
+    S0 = np.zeros((p, s.stride), dtype=np.uint8)
+    for i in range(p):
+        for v in range(I.nv):
+            choices = [0] + list(dom[off[v]:off[v + 1]])
+            S0[i, v] = choices[rng.integers(0, len(choices))]
+    import torch
+    S1, f1, c1 = s.stage_plits(torch.from_numpy(S0).cuda(), 4, 321)
+    torch.cuda.synchronize()
+    Po = I.params(depth=4000)
+    Po[oracle_mod.P_ALPHA_NUM], Po[oracle_mod.P_ALPHA_DEN] = 3, 1
+    S1o, f1o, c1o = I.plits(Po, 321, 4, list(range(p)), S0[:, :I.nv])
+    np.testing.assert_array_equal(_np(S1)[:, :I.nv], S1o)
+    np.testing.assert_array_equal(_np(f1), f1o)
+    np.testing.assert_array_equal(_np(c1).astype(np.uint64), c1o)
 
 
 # --- Partial-MPMA (Section 3.7) --------------------------------------------------------
