@@ -7,15 +7,24 @@ HBM before the timed region; W warmup generations run first, then exactly K
 generations are timed (device synchronised on both sides).
 
 value = tabu moves executed in the K timed generations / their wall time.
-roofline: the tabu-search kernel is bound by integer ALU issue (its state is
-LDS-resident and small; see plits_alg_ops): algorithmic integer operations
-per launch, from the per-generation counters, over its mean launch time from
-HIP events recorded on the launch stream, against the int32 VALU peak.
+roofline: the tabu-search kernel against the LDS level, where the search
+state it touches per move lives: algorithmic bytes per launch from the
+per-generation counters (per move: every candidate's conflict and tabu
+entries, the conflict-table entries of the moved vertex's neighbours, the
+eligibility scan, the colour and tabu writes, snapshots; 2-byte conflict and
+tabu entries) over the launch's mean time from HIP events on its stream,
+against the LDS read bandwidth measured on this GPU in the same run.  The
+same launch's integer-operation rate against the int32 VALU peak is given
+beside it.
 traffic: HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
 WRITE_SIZE summary of this command, scaled by the copy-kernel factors stated
 in it; null when the kernel sources changed since it was taken.
-cpu_baseline: the CPU oracle's PLITS on a bounded sample of the same
-generation-1 population, on the host's cores.
+cpu_baseline: the CPU oracle's PLITS on a bounded sample of the offspring the
+GPU searched in the first timed generation (read from a checkpoint taken
+after the warmup), on the host's cores; the generation-1 pair beside it.
+sustained: a few generations of the 70x70 grid 70 % prefilled (p = 16384,
+depth 49000), whose searches never complete, so every generation is full.
+stages_ms: per-stage GPU times of a separate stage-timed run (plse_last_stage_timing).
 """
 
 from __future__ import annotations
@@ -24,6 +33,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -33,12 +43,12 @@ sys.path.insert(0, ROOT)
 import hashlib
 
 HBM_PEAK_GBS = 8000.0
-# LDS: 256 CUs x 128 B/clk x 2.4 GHz (nominal)
-LDS_PEAK_GBS = 256 * 128 * 2.4
 # int32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PLITS_SOURCES = ["k_plits.hip", "device_common.h", "kernels.h", "plse_internal.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plits_n50_hbm.txt")
+# bytes per conflict-table entry and per tabu entry in the algorithmic count
+B_CONF, B_TABU = 2, 2
 
 
 def plits_alg_ops(cnt, n, nv):
@@ -53,13 +63,27 @@ def plits_alg_ops(cnt, n, nv):
     bookkeeping (10).  Per move (moves): 8 for the counts, colour and
     objective, 3 per row/column vertex re-checked (2|V|/n on average).  Per
     snapshot (snaps): |V|/4 word copies.
-    cnt: counters [iters, moves, idle, cands, elig, nupd, snaps, repairs].
+    cnt: counters [iters, moves, idle, cands, elig, nupd, snaps, repairs, cupd].
     """
     iters, moves, cands, elig, snaps = (int(cnt[0]), int(cnt[1]), int(cnt[3]), int(cnt[4]),
                                         int(cnt[6]))
     per_iter = 2 * ((nv + 31) // 32) + 7 * (n + 1) + 10
     per_move = 8 + 3 * (2 * nv // n)
     return cands * 10 + elig * 10 + iters * per_iter + moves * per_move + snaps * (nv // 4)
+
+
+def plits_alg_bytes(cnt, nv):
+    """Algorithmic bytes of one tabu-search launch (Section 3.3's incremental
+    evaluation): per candidate move its conflict entry and tabu entry read;
+    per neighbour of the moved vertex and coloured end of the move, one
+    conflict entry read and written; per iteration the eligibility scan
+    (|V| / 8); per move the colour and the tabu entry written; per snapshot
+    |V| colours.
+    cnt: counters [iters, moves, idle, cands, elig, nupd, snaps, repairs, cupd]."""
+    iters, moves, cands, nupd, snaps = (int(cnt[0]), int(cnt[1]), int(cnt[3]), int(cnt[5]),
+                                        int(cnt[6]))
+    return (cands * (B_CONF + B_TABU) + nupd * 2 * B_CONF + iters * ((nv + 7) // 8)
+            + moves * (1 + B_TABU) + snaps * nv)
 
 
 def plits_sources_sha256():
@@ -93,41 +117,30 @@ def plits_traffic(warmup, steps, workload):
     return sum((fk * ff + wk * wf) * 1024.0 for _, fk, wk in timed) / steps
 
 
-def plits_state_bytes(cnt, p, n, nv):
-    """Algorithmic bytes of search state one tabu-search launch touches.
-
-    The state of an individual is its colouring S (1 B per vertex), the row and
-    column colour counts (1 B each), the eligibility bitmap and the tabu table.
-    Per iteration: the bitmap (|V|/8 B); per eligible vertex its colour and
-    the two counts of that colour (3 B); per candidate move the two counts of
-    the candidate colour (2 B).  Per move: four counts read and written (8 B),
-    the colour (1 B), one tabu entry (4 B) and the colours of the 2(n-1) row
-    and column vertices (2(n-1) B).  Per snapshot |V| B; per phase of every
-    individual the start row (|V| B).
-    cnt: counters [iters, moves, idle, cands, elig, nupd, snaps, repairs].
-    """
-    iters, moves, cands, elig, snaps = (int(cnt[0]), int(cnt[1]), int(cnt[3]), int(cnt[4]),
-                                        int(cnt[6]))
-    return (iters * ((nv + 7) // 8) + elig * 3 + cands * 2 + moves * (13 + 2 * (n - 1))
-            + snaps * nv + p * 2 * nv)
+def host_cpu():
+    """Model name and logical CPUs of the host (lscpu)."""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except Exception:
+        return None
+    info = {}
+    for line in out.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Socket(s)"):
+                info[k.strip()] = v.strip()
+    return info
 
 
-def cpu_baseline(grid, seed, depth, target_s=12.0):
-    """Oracle PLITS of generation 1 on a bounded sample of slots."""
-    from oracle import oracle as O
-    O.build()
-    I = O.Instance(grid)
-    P = I.params(depth=depth)
-    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    moves = 0
-    elapsed = 0.0
-    done = 0
+def _oracle_rate(I, P, seed, gen_no, S_rows, threads, target_s, label):
+    """Oracle PLITS moves/s over leading rows of S_rows, sized to ~target_s."""
+    moves, elapsed, done = 0, 0.0, 0
     k = threads
-    while True:
+    while done < len(S_rows):
+        k = min(k, len(S_rows) - done)
         slots = list(range(done, done + k))
-        S, _ = I.init_slots(seed, slots)
         t0 = time.perf_counter()
-        _, _, cnt = I.plits(P, seed, 1, slots, S)
+        _, _, cnt = I.plits(P, seed, gen_no, slots, S_rows[done:done + k])
         elapsed += time.perf_counter() - t0
         moves += int(cnt[:, 1].sum())
         done += k
@@ -135,9 +148,68 @@ def cpu_baseline(grid, seed, depth, target_s=12.0):
             break
         k = threads * max(1, int(math.ceil((target_s - elapsed) / max(elapsed, 1e-3) * done / threads)))
         k = min(k, 16 * threads)
-    return {"value": moves / elapsed, "unit": "moves/s", "cores": threads, "kind": "oracle",
-            "sample": f"generation-1 PLITS of slots 0..{done - 1} of the same population "
-                      f"({done} individuals, {moves} moves, {elapsed:.1f} s)"}
+    return {"value": moves / elapsed, "sample": f"{label}: slots 0..{done - 1} ({done} individuals, "
+                                                f"{moves} moves, {elapsed:.1f} s)"}
+
+
+def cpu_baseline(grid, seed, depth, gen_no, offspring, gpu_gen1, target_s=10.0):
+    """The oracle's PLITS on the offspring of generation gen_no (the first
+    timed generation), and on the initial population (generation 1)."""
+    from oracle import oracle as O
+    O.build()
+    I = O.Instance(grid)
+    P = I.params(depth=depth)
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    r = _oracle_rate(I, P, seed, gen_no, offspring, threads, target_s,
+                     f"generation-{gen_no} PLITS of the GPU's offspring")
+    S1, _ = I.init_slots(seed, list(range(min(4096, len(offspring)))))
+    r1 = _oracle_rate(I, P, seed, 1, S1, threads, target_s, "generation-1 PLITS")
+    return {"value": r["value"], "unit": "moves/s", "cores": threads, "kind": "oracle",
+            "sample": r["sample"], "host": host_cpu(),
+            "generation1": {"oracle_moves_per_s": r1["value"], "sample": r1["sample"],
+                            "gpu_moves_per_s": gpu_gen1}}
+
+
+def sustained_run(gen, plse, warmup=1, steps=3):
+    """Generations of the 70x70 grid 70 % prefilled, whose searches all run
+    to their full depth: moves/s with every generation busy."""
+    import torch
+    w = gen.workload_n70(0.7)
+    p = w["population"]
+    s = plse.Solver(w["grid"], depth=w["depth"])
+    s.ensure_workspace(p)
+    stream = torch.cuda.current_stream()
+    s.begin(p, w["seed"], stream)
+    s.step(warmup, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.end(stream)
+    st = s.stats()
+    ms_plits, _ = s.timing()
+    cnt = st["counters_per_gen"][warmup:warmup + steps]
+    moves = int(cnt[:, 1].sum())
+    out = {"workload": "random-greedy n=70, 70% prefilled, population 16384, depth 49000",
+           "warmup": warmup, "steps": steps, "moves_per_s": moves / wall,
+           "ms_per_step": wall / steps * 1e3,
+           "plits_ms_per_gen": [float(x) for x in ms_plits[warmup:warmup + steps]],
+           "moves_per_gen": [int(x) for x in cnt[:, 1]],
+           "best_f_per_gen": [int(x) for x in st["best_f_per_gen"]]}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def stage_times(plse, w, p, G=3):
+    """Per-stage GPU times of a stage-timed run of the same workload."""
+    s = plse.Solver(w["grid"], depth=w["depth"], stage_timing=1)
+    s.solve(p, G, w["seed"])
+    st = s.stage_timing()
+    return {"generations": G, "mean_ms_after_generation_1": {
+        name: float(st[1:, i].mean()) for i, name in enumerate(plse.STAGES)},
+        "generation_1_ms": {name: float(st[0, i]) for i, name in enumerate(plse.STAGES)}}
 
 
 def main():
@@ -166,7 +238,11 @@ def main():
     ap.add_argument("--slots-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--population", type=int, default=0)
+    ap.add_argument("--plits-kernel", type=int, default=0, choices=[0, 1, 2],
+                    help="tabu-search kernel: 0/1 global tabu table, 2 LDS-resident")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sustained", action="store_true",
+                    help="skip the sustained-throughput generations of the 70x70 grid")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise device copy of MIB MiB (reads MIB, "
                          "writes MIB), the reference for scaling HBM byte counters")
@@ -219,12 +295,21 @@ def main():
     p = w["population"]
     torch.cuda.set_device(0)
     s = plse.Solver(w["grid"], depth=w["depth"], slots_per_lane=args.slots_per_lane,
-                    waves_per_block=args.waves_per_block, variant=args.variant)
+                    waves_per_block=args.waves_per_block, variant=args.variant,
+                    plits_kernel=args.plits_kernel)
     s.ensure_workspace(p)
     stream = torch.cuda.current_stream()
 
     s.begin(p, w["seed"], stream)
     s.step(args.warmup, stream)
+    torch.cuda.synchronize()
+    # the offspring the first timed generation searches (for the CPU
+    # baseline); the image ends with them (include/plse.h)
+    offspring = None
+    if not args.no_cpu_baseline and args.workload == "n50" and args.warmup >= 1:
+        img = s.checkpoint(stream)
+        offspring = np.asarray(img[len(img) - p * s.stride:]).reshape(p, s.stride)[:, :s.nv].copy()
+        del img
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(args.steps, stream)
@@ -239,13 +324,19 @@ def main():
     moves_timed = int(cnt[timed, 1].sum())
     wall = t1 - t0
     value = moves_timed / wall
-    bytes_gen = [plits_state_bytes(cnt[g], p, s.n, s.nv) for g in range(timed.start, timed.stop)]
-    ops_gen = [plits_alg_ops(cnt[g], s.n, s.nv) for g in range(timed.start, timed.stop)]
     t_plits = [float(ms_plits[g]) for g in range(timed.start, timed.stop)]
     t_mean = np.mean(t_plits) * 1e-3
-    achieved = (sum(ops_gen) / max(len(ops_gen), 1)) / t_mean / 1e12
-    lds_gbs = (sum(bytes_gen) / max(len(bytes_gen), 1)) / t_mean / 1e9
+    bytes_gen = [plits_alg_bytes(cnt[g], s.nv) for g in range(timed.start, timed.stop)]
+    ops_gen = [plits_alg_ops(cnt[g], s.n, s.nv) for g in range(timed.start, timed.stop)]
+    b_launch = sum(bytes_gen) / max(len(bytes_gen), 1)
+    achieved = b_launch / t_mean / 1e9
+    alu = (sum(ops_gen) / max(len(ops_gen), 1)) / t_mean / 1e12
+    lds_peak = plse.plse_measure_lds_bandwidth(5) / 1e9
     traffic = plits_traffic(args.warmup, args.steps, args.workload)
+    kernel = "plits_%skernel<%d%s>" % ("lean_" if s.get_param("plits_kernel") == 2 else "",
+                                       int(s.get_param("slots_per_lane")),
+                                       "" if s.get_param("plits_kernel") == 2 else
+                                       (", true" if args.variant else ", false"))
     out = {
         "metric": "tabu moves/s (n=50, pop 16384)" if args.workload == "n50" and not args.variant
         else f"tabu moves/s ({args.workload}{', Partial-MPMA' if args.variant else ''}, pop {p})",
@@ -265,21 +356,27 @@ def main():
                    "slots_per_lane": int(s.get_param("slots_per_lane")),
                    "vertices": s.nv, "sum_domain": s.nd,
                    "waves_per_block": int(s.get_param("waves_per_block"))},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "plits_kernel<%d, %s>" % (int(s.get_param("slots_per_lane")),
-                                                          "true" if args.variant else "false"),
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": lds_peak, "unit": "GB/s",
+                     "frac": achieved / lds_peak, "traffic": traffic, "kernel": kernel,
+                     "bytes_per_launch": b_launch,
+                     "bytes_per_move": b_launch / max(moves_timed / max(len(bytes_gen), 1), 1),
+                     "launch_ms": t_mean * 1e3,
+                     "peak_source": "plse_measure_lds_bandwidth: conflict-free 16-byte LDS "
+                                    "reads on every CU, this GPU, this run",
                      "hbm_gbs": (traffic / t_mean / 1e9) if traffic else None,
                      "hbm_frac": (traffic / t_mean / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                     "lds_state_gbs": lds_gbs, "lds_state_frac": lds_gbs / LDS_PEAK_GBS},
+                     "alu": {"achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                             "frac": alu / ALU_PEAK_TOPS}},
         "detail": {"moves_timed": moves_timed, "plits_ms_per_gen": t_plits,
                    "rest_ms_per_gen": [float(ms_rest[g]) for g in range(timed.start, timed.stop)],
-                   "plits_state_bytes_per_gen": bytes_gen,
+                   "plits_alg_bytes_per_gen": bytes_gen,
                    "plits_alg_ops_per_gen": ops_gen,
                    "moves_per_gen": [int(x) for x in cnt[:, 1]],
                    "iters_per_gen": [int(x) for x in cnt[:, 0]],
                    "cands_per_gen": [int(x) for x in cnt[:, 3]],
                    "elig_per_gen": [int(x) for x in cnt[:, 4]],
+                   "nupd_per_gen": [int(x) for x in cnt[:, 5]],
+                   "snaps_per_gen": [int(x) for x in cnt[:, 6]],
                    "best_f_per_gen": [int(x) for x in st["best_f_per_gen"]],
                    "filled": filled, "upper_bound": s.ub,
                    "plits_moves_per_s": moves_timed / (sum(t_plits) * 1e-3),
@@ -288,8 +385,16 @@ def main():
                                          "moves_per_s": float(cnt[0, 1]) / (float(ms_plits[0]) * 1e-3)}
                                         if args.warmup >= 1 and gens >= 1 else None)},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w["grid"], w["seed"], w["depth"])
+    del s
+    torch.cuda.empty_cache()
+    if args.workload == "n50" and not args.variant:
+        out["stages_ms"] = stage_times(plse, w, p)
+        if not args.no_sustained:
+            out["sustained"] = sustained_run(gen, plse)
+    if offspring is not None:
+        g1 = out["detail"]["first_generation"]
+        out["cpu_baseline"] = cpu_baseline(w["grid"], w["seed"], w["depth"], args.warmup + 1,
+                                           offspring, g1["moves_per_s"] if g1 else None)
     print(json.dumps(out), flush=True)
 
 

@@ -113,6 +113,14 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *                 round (default 0: chosen from the domain sizes)
  *   "waves_per_block" 1, 2 or 4: PLITS launch shape (default: chosen from the
  *                 LDS footprint)
+ *   "plits_kernel" 1: the tabu-search kernel with each individual's tabu
+ *                 table in global memory (the default, also 0); 2: the kernel
+ *                 with the whole search state in LDS (MPMA only, when it fits
+ *                 the device's per-block LDS).  Both give the same results.
+ *   "stage_timing" 1: single-instance sessions enqueue each stage of a
+ *                 generation on its own between HIP events (no graphs; the
+ *                 distances among P_t run before the search instead of
+ *                 beside it), for plse_last_stage_timing; results unchanged
  *   "max_generations" 1..65536: the most generations one session of this
  *                 handle may run (65536); the workspace holds one statistics
  *                 record (80 bytes) per generation, so a smaller value
@@ -295,6 +303,16 @@ int plse_measure_lds_bandwidth(void *stream, int32_t repeats, double *bytes_per_
  * rest_ms[g] the best/distance/selection/matching/crossover kernels.  *steps
  * receives the number of generations stepped; either array may be NULL. */
 int plse_last_timing(plse_handle h, int32_t *steps, float *plits_ms, float *rest_ms);
+
+/* Per-stage GPU times (ms) of the last single-instance session run with the
+ * "stage_timing" parameter set: PLSE_NSTAGES floats per generation, in the
+ * order of Alg. 2's steps -- distances among P_t (Eq. 8), the tabu searches
+ * (Alg. 3), best-solution saving, distances between P' and P_t u P', the
+ * population update (Alg. 4: close-pair lists, selection, gather), parent
+ * matching (Section 3.5.1) and AUX crossover (Eq. 9, Alg. 5).  *steps
+ * receives the generations timed (0 without stage timing); ms may be NULL. */
+#define PLSE_NSTAGES 7
+int plse_last_stage_timing(plse_handle h, int32_t *steps, float *ms);
 
 /* Statistics of the last solve; per_gen_best_f (may be NULL) receives the
  * best f after each generation (generations_run entries) and per_gen_counters

@@ -118,6 +118,8 @@ struct plse_instance {
     std::vector<int32_t> gen_best;
     std::vector<uint64_t> gen_cnt;
     std::vector<float> ms_plits, ms_rest;
+    int stage_timing = 0;           // time every stage of a generation (no graphs)
+    std::vector<float> ms_stages;   // [generations][kStages] of the last session
     std::atomic<int> busy{0};
 };
 
@@ -540,6 +542,9 @@ struct PlitsGroup {
     std::vector<plse_instance *> hs;
 };
 
+// Stages of a generation timed by the stage-timing mode (plse_last_stage_timing).
+constexpr int kStages = 7;
+
 // A solve over one or many instances sharing the population size.
 struct Session {
     std::vector<plse_instance *> hs;  // launch order: longest estimated work first
@@ -550,6 +555,8 @@ struct Session {
     std::vector<PlitsGroup> groups;  // largest estimated work first
     hipGraphExec_t ls = nullptr, rest = nullptr;  // ls only with a single group
     std::vector<hipEvent_t> ev;                   // 3 per generation
+    bool staged = false;                          // stage timing: kStages + 1 events per generation
+    std::vector<hipEvent_t> sev;
     std::vector<hipStream_t> side;                // groups 1.. of a generation
     std::vector<hipEvent_t> fork;                 // 1 + one per side stream
     // distances among P_t, beside the searches: graph, stream, fork / join
@@ -576,6 +583,7 @@ struct Session {
         if (ls) (void)hipGraphExecDestroy(ls);
         if (rest) (void)hipGraphExecDestroy(rest);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : sev) (void)hipEventDestroy(e);
         for (hipStream_t q : side) {
             (void)hipStreamSynchronize(q);
             (void)hipStreamDestroy(q);
@@ -643,13 +651,18 @@ int enqueue_old_dist(Session &S, hipStream_t s) {
     return enqueue_pack_dist(S, &ArgBlock::pack_t, &ArgBlock::dist_t, S.p, old_tiles(S.p), s);
 }
 
-int enqueue_rest(Session &S, hipStream_t s) {
+// The generation's stages after the searches.  `mark` (may be null) records
+// an event after each stage: best, distances with P', selection (close,
+// select, gather), matching (hash, match); the crossover ends the sequence.
+int enqueue_rest(Session &S, hipStream_t s, hipEvent_t *mark = nullptr) {
     const int p = S.p, m = 2 * p;
     RC_TRY(launch_over(S.hs, &ArgBlock::best,
                        [&](const ArgList &L, int c) { return launch_best(L, c, s); }));
+    if (mark) HIP_TRY(hipEventRecord(mark[0], s));
     const long nt1 = (m + kDistTile - 1) / kDistTile;
     RC_TRY(enqueue_pack_dist(S, &ArgBlock::pack, &ArgBlock::dist, old_tiles(p) > 0 ? p : m,
                              nt1 * (nt1 + 1) / 2 - old_tiles(p), s));
+    if (mark) HIP_TRY(hipEventRecord(mark[1], s));
     RC_TRY(launch_over(S.hs, &ArgBlock::close,
                        [&](const ArgList &L, int c) { return launch_close(L, c, m, s); }));
     const size_t sl = select_lds(S.hs[0], p);
@@ -660,11 +673,13 @@ int enqueue_rest(Session &S, hipStream_t s) {
     }));
     RC_TRY(launch_over(S.hs, &ArgBlock::gather,
                        [&](const ArgList &L, int c) { return launch_gather(L, c, p, s); }));
+    if (mark) HIP_TRY(hipEventRecord(mark[2], s));
     const int hsize = S.hs[0]->L.hsize;
     RC_TRY(launch_over(S.hs, &ArgBlock::hash,
                        [&](const ArgList &L, int c) { return launch_hash(L, c, p, hsize, s); }));
     RC_TRY(launch_over(S.hs, &ArgBlock::match,
                        [&](const ArgList &L, int c) { return launch_match(L, c, p, s); }));
+    if (mark) HIP_TRY(hipEventRecord(mark[3], s));
     RC_TRY(launch_over(S.hs, &ArgBlock::aux,
                        [&](const ArgList &L, int c) { return launch_aux(L, c, p, s); }));
     return PLSE_OK;
@@ -773,6 +788,11 @@ int session_begin(Session &S, const uint64_t *seeds, hipStream_t s) {
     shape_session(S);
     // a single group's generation is one graph; several groups are enqueued
     // on forked streams each generation, so they run side by side
+    S.staged = S.hs.size() == 1 && S.hs[0]->stage_timing != 0;
+    if (S.staged) {
+        S.steps = 0;
+        return PLSE_OK;  // stages enqueued one by one, each bracketed by events
+    }
     if (S.groups.size() == 1)
         RC_TRY(capture([&](hipStream_t cs) { return enqueue_local_search(S, cs); }, &S.ls));
     RC_TRY(capture([&](hipStream_t cs) { return enqueue_rest(S, cs); }, &S.rest));
@@ -793,6 +813,31 @@ int session_step(Session &S, int generations, hipStream_t s) {
         hipEvent_t e = nullptr;
         HIP_TRY(hipEventCreate(&e));
         S.ev.push_back(e);
+    }
+    if (S.staged) {
+        // distances among P_t, search, best, distances with P', selection,
+        // matching, crossover: one after another on `s`
+        while (S.sev.size() < (kStages + 1) * (size_t)(S.steps + generations)) {
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipEventCreate(&e));
+            S.sev.push_back(e);
+        }
+        for (int g = 0; g < generations; ++g) {
+            const size_t k = 3 * (size_t)(S.steps + g);
+            hipEvent_t *m = &S.sev[(kStages + 1) * (size_t)(S.steps + g)];
+            HIP_TRY(hipEventRecord(m[0], s));
+            if (old_tiles(S.p) > 0) RC_TRY(enqueue_old_dist(S, s));
+            HIP_TRY(hipEventRecord(m[1], s));
+            HIP_TRY(hipEventRecord(S.ev[k], s));
+            RC_TRY(enqueue_local_search(S, s));
+            HIP_TRY(hipEventRecord(S.ev[k + 1], s));
+            HIP_TRY(hipEventRecord(m[2], s));
+            RC_TRY(enqueue_rest(S, s, &m[3]));
+            HIP_TRY(hipEventRecord(m[7], s));
+            HIP_TRY(hipEventRecord(S.ev[k + 2], s));
+        }
+        S.steps += generations;
+        return PLSE_OK;
     }
     for (int g = 0; g < generations; ++g) {
         const size_t k = 3 * (size_t)(S.steps + g);
@@ -848,6 +893,15 @@ int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &o
         HIP_TRY(hipEventElapsedTime(&tp[g], S.ev[3 * g], S.ev[3 * g + 1]));
         HIP_TRY(hipEventElapsedTime(&tr[g], S.ev[3 * g + 1], S.ev[3 * g + 2]));
     }
+    std::vector<float> tst;
+    if (S.staged && S.sev.size() >= (kStages + 1) * (size_t)S.steps) {
+        tst.resize((size_t)kStages * S.steps);
+        for (int g = 0; g < S.steps; ++g)
+            for (int q = 0; q < kStages; ++q)
+                HIP_TRY(hipEventElapsedTime(&tst[(size_t)kStages * g + q],
+                                            S.sev[(kStages + 1) * (size_t)g + q],
+                                            S.sev[(kStages + 1) * (size_t)g + q + 1]));
+    }
     for (size_t i = 0; i < S.hs.size(); ++i) {
         plse_instance *h = S.hs[i];
         const int gens = std::min(ctl[i].gens_run, G);  // every stepped generation has ended
@@ -857,6 +911,7 @@ int session_end(Session &S, hipStream_t s, const std::vector<plse_instance *> &o
         h->gen_cnt = std::move(rr.gen_cnt);
         h->ms_plits = tp;
         h->ms_rest = tr;
+        h->ms_stages = tst;
         const size_t slot = (size_t)(std::find(order.begin(), order.end(), h) - order.begin());
         filled[slot] = best_grid(h->n, h->cell_v, h->grid, star[i].data(), gens, grids[slot]);
     }
@@ -1151,6 +1206,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "plits_kernel") {
         if (v < 0 || v > 2) return PLSE_E_PARAM;
         h->kernel = (int)v;
+    } else if (k == "stage_timing") {
+        if (v != 0 && v != 1) return PLSE_E_PARAM;
+        h->stage_timing = (int)v;
     } else if (k == "select_global_sort") {
         if (v != 0 && v != 1) return PLSE_E_PARAM;
         h->sel_global = (int)v;
@@ -1190,6 +1248,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "max_generations") *v = h->max_gens;
     else if (k == "select_global_sort") *v = h->sel_global;
     else if (k == "plits_kernel") *v = plits_lds(h).lean ? 2 : 1;
+    else if (k == "stage_timing") *v = h->stage_timing;
     else return PLSE_E_PARAM;
     return PLSE_OK;
 }
@@ -1509,6 +1568,13 @@ int plse_last_timing(plse_handle h, int32_t *steps, float *plits_ms, float *rest
     *steps = (int32_t)h->ms_plits.size();
     if (plits_ms) std::copy(h->ms_plits.begin(), h->ms_plits.end(), plits_ms);
     if (rest_ms) std::copy(h->ms_rest.begin(), h->ms_rest.end(), rest_ms);
+    return PLSE_OK;
+}
+
+int plse_last_stage_timing(plse_handle h, int32_t *steps, float *ms) {
+    if (!h || !steps) return PLSE_E_ARG;
+    *steps = (int32_t)(h->ms_stages.size() / kStages);
+    if (ms) std::copy(h->ms_stages.begin(), h->ms_stages.end(), ms);
     return PLSE_OK;
 }
 

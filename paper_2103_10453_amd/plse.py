@@ -85,6 +85,7 @@ def _lib():
             "plse_checkpoint": [P, P, P, sz, P],
             "plse_resume": [P, i32, P, P, sz],
             "plse_last_timing": [P, P, P, P],
+            "plse_last_stage_timing": [P, P, P],
             "plse_last_stats": [P, P, P, P],
             "plse_stage_init": [P, i32, u64, P, P, P],
             "plse_stage_plits": [P, i32, i32, u64, P, P, P, P, P],
@@ -122,7 +123,7 @@ def exported_symbols():
              "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
              "plse_solve_noalloc", "plse_measure_lds_bandwidth",
              "plse_begin",
-             "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_checkpoint", "plse_resume", "plse_last_timing", "plse_last_stats",
+             "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_checkpoint", "plse_resume", "plse_last_timing", "plse_last_stage_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
              "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux",
              "plse_server_create", "plse_server_submit", "plse_server_poll", "plse_server_status",
@@ -306,6 +307,19 @@ def plse_last_timing(h):
     return a[:k.value], b[:k.value]
 
 
+STAGES = ["distances_Pt", "tabu_search", "best", "distances_new", "selection", "matching",
+          "crossover"]
+
+
+def plse_last_stage_timing(h):
+    """Per-stage ms of the last stage-timed session: array [generations, 7]."""
+    k = ctypes.c_int32()
+    _check(_lib().plse_last_stage_timing(h, ctypes.byref(k), None), "plse_last_stage_timing")
+    a = np.zeros((max(k.value, 1), len(STAGES)), dtype=np.float32)
+    _check(_lib().plse_last_stage_timing(h, ctypes.byref(k), _np(a)), "plse_last_stage_timing")
+    return a[:k.value]
+
+
 def plse_last_stats(h):
     st = Stats()
     _check(_lib().plse_last_stats(h, ctypes.byref(st), None, None), "plse_last_stats")
@@ -438,6 +452,9 @@ class Solver:
 
     def stats(self):
         return plse_last_stats(self.h)
+
+    def stage_timing(self):
+        return plse_last_stage_timing(self.h)
 
     @staticmethod
     def solve_batch(solvers, population: int, generations: int, seeds, stream=None):

@@ -49,3 +49,14 @@ def test_operation_model_counts():
     per_move = 8 + 3 * 12
     want = 100 * 10 + 20 * 10 + 10 * per_iter + 9 * per_move + 2 * 15
     assert bench.plits_alg_ops(cnt, n, nv) == want
+
+
+def test_algorithmic_bytes_follow_the_move_definition():
+    # iters, moves, idle, cands, elig, nupd, snaps, repairs, cupd
+    cnt = [10, 9, 1, 100, 20, 36, 2, 0, 36]
+    nv = 60
+    # candidates: conflict + tabu entry read (2 + 2 bytes); neighbour updates:
+    # one 2-byte conflict entry read and written; scan |V|/8 per iteration;
+    # colour (1) and tabu entry (2) per move; |V| per snapshot
+    want = 100 * 4 + 36 * 4 + 10 * 8 + 9 * 3 + 2 * 60
+    assert bench.plits_alg_bytes(cnt, nv) == want

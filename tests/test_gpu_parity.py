@@ -395,6 +395,30 @@ def test_solve_repeatable_and_shape_independent(torch_cuda):
     assert len(set(outs)) == 1
 
 
+@pytest.mark.parametrize("p", [40, 200])
+def test_stage_timing_keeps_results(torch_cuda, p):
+    """The stage-timed mode (stages one by one between events, distances among
+    P_t before the search) gives the graph-replay result, with a positive time
+    for every stage of every generation (p >= 64: distances among P_t are a
+    stage of their own)."""
+    g = gen.random_greedy(20, 0.5, 7)
+    _say(f"stage timing p={p}")
+    s = P.Solver(g, depth=2000)
+    ref = s.solve(p, 3, 5)
+    ref_tot = s.stats()["totals"].copy()
+    assert s.stage_timing().shape == (0, len(P.STAGES))
+    s.set_param("stage_timing", 1)
+    grid, filled = s.solve(p, 3, 5)
+    assert filled == ref[1] and np.array_equal(grid, ref[0])
+    assert np.array_equal(s.stats()["totals"], ref_tot)
+    st = s.stage_timing()
+    assert st.shape == (3, len(P.STAGES))
+    cols = [i for i, name in enumerate(P.STAGES) if p >= 64 or name != "distances_Pt"]
+    assert (st[:, cols] > 0).all()
+    ms_plits, _ = s.timing()
+    np.testing.assert_allclose(st[:, 1], ms_plits, rtol=0.25, atol=0.05)
+
+
 # --- full size: sampled individuals --------------------------------------------------
 def test_full_size_n50_generation_sampled(torch_cuda, oracle_mod):
     """Planted n=50, 50% prefilled, population 16384, depth 10 n^2 as timed by
