@@ -225,8 +225,21 @@ def main():
     ap.add_argument("--instances", type=int, default=256, help="batch: number of instances")
     ap.add_argument("--autotune", action="store_true",
                     help="batch: pick each instance's launch shape by measurement first")
+    ap.add_argument("--batch-part", default="both", choices=["both", "batched", "sequential"],
+                    help="batch: run both halves, or one (see --results-file)")
+    ap.add_argument("--batch-chunk", type=int, default=5,
+                    help="batch: generations stepped between progress lines")
+    ap.add_argument("--results-file", default="",
+                    help="batch with one half: save its grids here, or compare with the "
+                         "other half's saved grids if the file exists; served: where the "
+                         "solo part saves its results and the served part reads them")
     ap.add_argument("--requests", type=int, default=16, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
+    ap.add_argument("--rates", default="",
+                    help="served: comma-separated arrival rates (one JSON line each)")
+    ap.add_argument("--served-part", default="both", choices=["both", "solo", "served"],
+                    help="served: run the solo baseline, the served streams, or both "
+                         "(see --results-file)")
     ap.add_argument("--max-slots", type=int, default=64,
                     help="served: requests resident at once (admission limit)")
     ap.add_argument("--generations", type=int, default=0,
@@ -399,8 +412,11 @@ def main():
 
 
 def bench_batch(args, gen, plse):
-    """Many instances per launch (plse_solve_batch) vs one plse_solve per
-    instance, same seeds and generations: results must be identical."""
+    """Many instances at once (batched session: per generation one persistent
+    search launch per launch-shape group) vs one plse_solve per instance, same
+    seeds and generations: results must be identical.  Both halves report
+    progress as they go; --batch-part runs one half (results saved to / compared
+    with --results-file) so that long configurations fit separate runs."""
     import numpy as np
     import torch
     torch.cuda.set_device(0)
@@ -409,6 +425,7 @@ def bench_batch(args, gen, plse):
     solvers = [plse.Solver(w["grid"], depth=w["depth"]) for w in work]
     p = work[0]["population"]
     seeds = [w["seed"] for w in work]
+    ns = [int(w["grid"].shape[0]) for w in work]
     for s in solvers:
         s.ensure_workspace(p)
     t_tune = None
@@ -416,38 +433,76 @@ def bench_batch(args, gen, plse):
         # measured launch shapes per instance (results do not depend on them)
         t0 = time.perf_counter()
         for s, w in zip(solvers, work):
-            s.autotune(sample=p, depth=500, seed=w["seed"])
+            s.autotune_shape(sample=p, depth=500, seed=w["seed"])
         torch.cuda.synchronize()
         t_tune = time.perf_counter() - t0
     shapes = {}
     for s in solvers:
         k = f"{s.get_param('slots_per_lane')}x{s.get_param('waves_per_block')}"
         shapes[k] = shapes.get(k, 0) + 1
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res_b = plse.Solver.solve_batch(solvers, p, G, seeds)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    moves_b = sum(int(s.stats()["totals"][1]) for s in solvers)
-    t0 = time.perf_counter()
-    res_s = [s.solve(p, G, w["seed"]) for s, w in zip(solvers, work)]
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    moves_s = sum(int(s.stats()["totals"][1]) for s in solvers)
-    same = all(a[1] == b[1] and np.array_equal(a[0], b[0]) for a, b in zip(res_b, res_s))
-    print(json.dumps({
-        "metric": f"batched tabu moves/s ({len(work)} instances, pop {p}, {G} generations)",
-        "value": moves_b / t_batch, "unit": "moves/s", "n_gpus": 1, "steps": G, "warmup": 0,
-        "ms_per_step": t_batch / G * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "batch: n ~ U{20..70}, r ~ U[0.3, 0.7], half planted, half "
-                               "random-greedy, population 1024, depth 10n^2",
-                   "instances": len(work), "population": p,
-                   "launch_shapes": "autotuned" if args.autotune else "cost model"},
-        "shapes": shapes, "autotune_seconds": t_tune,
-        "one_instance_per_launch": {"value": moves_s / t_seq, "seconds": t_seq},
-        "batched_seconds": t_batch, "speedup": t_seq / t_batch, "identical_results": same,
-        "filled_total": int(sum(r[1] for r in res_b))}), flush=True)
+    out = {"metric": f"batched tabu moves/s ({len(work)} instances, pop {p}, {G} generations)",
+           "value": None, "unit": "moves/s", "n_gpus": 1, "steps": G, "warmup": 0,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "batch: n ~ U{20..70}, r ~ U[0.3, 0.7], half planted, half "
+                                  "random-greedy, population 1024, depth 10n^2",
+                      "instances": len(work), "population": p,
+                      "launch_shapes": "autotuned" if args.autotune else "cost model",
+                      "search_launch": "one persistent launch per launch-shape group and "
+                                       "generation, waves taking (instance, individual) items "
+                                       "longest estimated work first"},
+           "shapes": shapes, "autotune_seconds": t_tune}
+    res_b = res_s = None
+    stream = torch.cuda.current_stream()
+    if args.batch_part in ("both", "batched"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = plse.plse_batch_begin([s.h for s in solvers], p, seeds, stream)
+        done = 0
+        while done < G:
+            k = min(args.batch_chunk, G - done)
+            plse.plse_batch_step(b, k, stream)
+            torch.cuda.synchronize()
+            done += k
+            print(f"[batch] batched: {done}/{G} generations, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+        res_b = plse.plse_batch_end(b, ns, stream)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        moves_b = sum(int(s.stats()["totals"][1]) for s in solvers)
+        out.update({"value": moves_b / t_batch, "ms_per_step": t_batch / G * 1e3,
+                    "batched_seconds": t_batch, "batched_moves": moves_b})
+    if args.batch_part in ("both", "sequential"):
+        t0 = time.perf_counter()
+        res_s = []
+        for i, (s, w) in enumerate(zip(solvers, work)):
+            res_s.append(s.solve(p, G, w["seed"]))
+            if (i + 1) % 16 == 0 or i + 1 == len(work):
+                print(f"[batch] one instance per launch: {i + 1}/{len(work)} instances, "
+                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        moves_s = sum(int(s.stats()["totals"][1]) for s in solvers)
+        out["one_instance_per_launch"] = {"value": moves_s / t_seq, "seconds": t_seq,
+                                          "moves": moves_s}
+    mine = res_b if res_b is not None else res_s
+    if args.results_file and args.batch_part != "both":
+        other = args.results_file if os.path.exists(args.results_file) else None
+        if other is None:
+            np.savez(args.results_file, filled=np.array([r[1] for r in mine]),
+                     **{f"g{i}": r[0] for i, r in enumerate(mine)})
+        else:
+            z = np.load(other)
+            out["identical_results"] = bool(all(
+                int(z["filled"][i]) == r[1] and np.array_equal(z[f"g{i}"], r[0])
+                for i, r in enumerate(mine)))
+            out["compared_with"] = os.path.basename(other)
+    if res_b is not None and res_s is not None:
+        out["speedup"] = out["one_instance_per_launch"]["seconds"] / out["batched_seconds"]
+        out["identical_results"] = all(a[1] == b_[1] and np.array_equal(a[0], b_[0])
+                                       for a, b_ in zip(res_b, res_s))
+    out["filled_total"] = int(sum(r[1] for r in mine))
+    print(json.dumps(out), flush=True)
 
 
 def bench_lsc(args, gen, plse):
@@ -485,72 +540,140 @@ def bench_lsc(args, gen, plse):
         "moves_per_s": moves / t_all if t_all else None, "cases": rows}), flush=True)
 
 
+def fifo_latencies(arrival, service):
+    """One request at a time in arrival order: start = max(arrival, previous
+    finish), finish = start + service; returns (start, finish)."""
+    start, finish, t = [], [], 0.0
+    for a, sv in zip(arrival, service):
+        st = max(a, t)
+        t = st + sv
+        start.append(st)
+        finish.append(t)
+    return start, finish
+
+
 def bench_served(args, gen, plse):
-    """Poisson request stream through the continuous-batching server vs the
-    same trace served one request at a time; same results required."""
+    """Poisson request streams through the continuous-batching server vs the
+    same streams served one request at a time; same results required.
+
+    The request set is the same at every rate (the gaps rescale).  Serving
+    one request at a time is measured once: each request solved alone on the
+    otherwise idle GPU (its solver and workspace prepared before its timer),
+    giving its service time and the offset of its best generation; the
+    one-at-a-time latencies of each rate follow by replaying the arrivals
+    through a single first-come first-served server with those service times.
+    --served-part solo / served splits the two halves over runs (the solo
+    results go to --results-file)."""
     import numpy as np
     import torch
     torch.cuda.set_device(0)
     G = args.generations or 50
-    reqs = gen.workload_served(args.requests, args.rate)
-    for r in reqs:
-        r["generations"] = G
-    p = reqs[0]["population"]
-    budget = int(0.6 * torch.cuda.get_device_properties(0).total_memory)
-    # served: submit at arrival times, poll until all are done
-    srv = plse.Server(budget, max_slots=args.max_slots)
-    solvers = [plse.Solver(r["grid"], depth=r["depth"]) for r in reqs]
-    tickets, results = [], {}
-    t0 = time.perf_counter()
-    i = 0
-    while len(results) < len(reqs):
-        now = time.perf_counter() - t0
-        while i < len(reqs) and reqs[i]["arrival"] <= now:
-            tickets.append((i, srv.submit(solvers[i], p, G, reqs[i]["seed"])))
-            i += 1
-        for k, t in tickets:
-            if k not in results:
-                r = srv.poll(t)
-                if r is not None:
-                    results[k] = r
-        time.sleep(0.001)
-    wall = time.perf_counter() - t0
-    srv.close()
-    del srv
-    lat = np.array([results[k]["done_s"] - results[k]["submit_s"] for k in range(len(reqs))])
-    ttb = np.array([results[k]["best_s"] - results[k]["submit_s"] for k in range(len(reqs))])
-    moves = sum(results[k]["moves"] for k in range(len(reqs)))
-    # baseline: the same arrivals, one plse_solve at a time in arrival order
-    base = []
-    t0 = time.perf_counter()
-    lat_b = []
-    for k, r in enumerate(reqs):
-        while time.perf_counter() - t0 < r["arrival"]:
-            time.sleep(0.0005)
-        s = plse.Solver(r["grid"], depth=r["depth"])
-        base.append(s.solve(p, G, r["seed"]))
-        lat_b.append(time.perf_counter() - t0 - r["arrival"])
-    wall_b = time.perf_counter() - t0
-    same = all(results[k]["filled"] == base[k][1] and np.array_equal(results[k]["grid"], base[k][0])
-               for k in range(len(reqs)))
+    rates = [float(x) for x in args.rates.split(",")] if args.rates else [args.rate]
+    unit = gen.workload_served(args.requests, 1.0)
+    p = unit[0]["population"]
     pct = lambda a, q: float(np.percentile(a, q))
-    print(json.dumps({
-        "metric": f"served requests/s (Poisson {args.rate}/s, {len(reqs)} requests, pop {p}, "
-                  f"{G} generations)",
-        "value": len(reqs) / wall, "unit": "requests/s", "n_gpus": 1, "steps": G, "warmup": 0,
-        "ms_per_step": wall / G * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "served: n ~ U{10..100}, r ~ U[0.3, 0.7], planted or "
-                               "random-greedy, population 2048, depth 10n^2",
-                   "requests": len(reqs), "rate": args.rate, "generations": G,
-                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
-                   "max_slots": args.max_slots},
-        "moves_per_s": moves / wall,
-        "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
-        "time_to_best_s": {"p50": pct(ttb, 50), "p99": pct(ttb, 99)},
-        "one_at_a_time": {"requests_per_s": len(reqs) / wall_b,
-                          "latency_s": {"p50": pct(lat_b, 50), "p99": pct(lat_b, 99)}},
-        "identical_results": same}), flush=True)
+    solvers = [plse.Solver(r["grid"], depth=r["depth"], max_generations=G) for r in unit]
+    solo = None
+    if args.served_part in ("both", "solo"):
+        svc, ttb_off, grids, filled, moves = [], [], [], [], 0
+        t_all = time.perf_counter()
+        for k, (s, r) in enumerate(zip(solvers, unit)):
+            s.ensure_workspace(p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g, f = s.solve(p, G, r["seed"])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = s.stats()
+            ms_p, ms_r = s.timing()
+            per_gen = (np.asarray(ms_p) + np.asarray(ms_r)) * 1e-3
+            setup = max(wall - float(per_gen.sum()), 0.0)
+            bg = max(int(st["best_generation"]), 1)
+            svc.append(wall)
+            ttb_off.append(setup + float(per_gen[:bg].sum()))
+            grids.append(g)
+            filled.append(f)
+            moves += int(st["totals"][1])
+            # the workspace goes before the next request's (and the server's arena)
+            plse.plse_attach_workspace(s.h, None)
+            s._ws = None
+            torch.cuda.empty_cache()
+            print(f"[served] solo {k + 1}/{len(unit)}: n={r['grid'].shape[0]} {wall:.2f} s "
+                  f"(total {time.perf_counter() - t_all:.1f} s)", file=sys.stderr, flush=True)
+        solo = dict(service=np.array(svc), ttb=np.array(ttb_off),
+                    filled=np.array(filled), moves=moves, grids=grids)
+        if args.results_file:
+            np.savez(args.results_file, service=solo["service"], ttb=solo["ttb"],
+                     filled=solo["filled"], moves=np.array([moves]),
+                     **{f"g{i}": g for i, g in enumerate(grids)})
+    elif args.results_file and os.path.exists(args.results_file):
+        z = np.load(args.results_file)
+        solo = dict(service=z["service"], ttb=z["ttb"], filled=z["filled"],
+                    moves=int(z["moves"][0]), grids=[z[f"g{i}"] for i in range(len(unit))])
+    if args.served_part == "solo":
+        print(json.dumps({"metric": f"solo service times ({len(unit)} requests, pop {p}, "
+                                    f"{G} generations)", "value": float(solo["service"].sum()),
+                          "unit": "s", "mean_s": float(solo["service"].mean()),
+                          "moves_per_s": solo["moves"] / float(solo["service"].sum())}),
+              flush=True)
+        return
+    free = torch.cuda.mem_get_info()[0]
+    budget = int(0.7 * free) // 256 * 256
+    for rate in rates:
+        reqs = [dict(r, arrival=r["arrival"] / rate) for r in unit]
+        srv = plse.Server(budget, max_slots=args.max_slots)
+        tickets, results = [], {}
+        t0 = time.perf_counter()
+        i = 0
+        while len(results) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i]["arrival"] <= now:
+                tickets.append((i, srv.submit(solvers[i], p, G, reqs[i]["seed"])))
+                i += 1
+            for k, t in tickets:
+                if k not in results:
+                    r = srv.poll(t)
+                    if r is not None:
+                        results[k] = r
+                        print(f"[served] rate {rate:g}: {len(results)}/{len(reqs)} done, "
+                              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            time.sleep(0.001)
+        wall = time.perf_counter() - t0
+        srv.close()
+        del srv
+        torch.cuda.empty_cache()
+        lat = np.array([results[k]["done_s"] - results[k]["submit_s"] for k in range(len(reqs))])
+        ttb = np.array([results[k]["best_s"] - results[k]["submit_s"] for k in range(len(reqs))])
+        moves = sum(results[k]["moves"] for k in range(len(reqs)))
+        row = {
+            "metric": f"served requests/s (Poisson {rate:g}/s, {len(reqs)} requests, pop {p}, "
+                      f"{G} generations)",
+            "value": len(reqs) / wall, "unit": "requests/s", "n_gpus": 1, "steps": G,
+            "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "served: n ~ U{10..100}, r ~ U[0.3, 0.7], planted or "
+                                   "random-greedy, population 2048, depth 10n^2",
+                       "requests": len(reqs), "rate": rate, "generations": G,
+                       "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+                       "max_slots": args.max_slots, "arena_bytes": budget},
+            "wall_s": wall, "moves_per_s": moves / wall,
+            "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+            "time_to_best_s": {"p50": pct(ttb, 50), "p99": pct(ttb, 99)}}
+        if solo is not None:
+            arr = [r["arrival"] for r in reqs]
+            st, fin = fifo_latencies(arr, solo["service"])
+            lat_b = np.array(fin) - np.array(arr)
+            ttb_b = np.array(st) + solo["ttb"] - np.array(arr)
+            row["one_at_a_time"] = {
+                "requests_per_s": len(reqs) / (fin[-1] - arr[0] if len(arr) else 1.0),
+                "moves_per_s": solo["moves"] / float(solo["service"].sum()),
+                "latency_s": {"p50": pct(lat_b, 50), "p99": pct(lat_b, 99)},
+                "time_to_best_s": {"p50": pct(ttb_b, 50), "p99": pct(ttb_b, 99)},
+                "method": "solo service times replayed first-come first-served"}
+            row["identical_results"] = bool(all(
+                results[k]["filled"] == int(solo["filled"][k]) and
+                np.array_equal(results[k]["grid"], solo["grids"][k]) for k in range(len(reqs))))
+        print(json.dumps(row), flush=True)
 
 
 if __name__ == "__main__":

@@ -76,7 +76,11 @@ typedef struct {
  */
 int plse_create(int32_t n, const int8_t *grid, plse_handle *out);
 
-/* |V| of the reduced graph, l (impossible cells), upper bound on the score. */
+/* Section 2.2 and Alg. 1: |V| (empty cells with a non-empty domain, the
+ * vertices of the reduced graph), l (empty cells whose domain is empty: they
+ * stay empty in every extension) and the upper bound on the score of
+ * Section 2.2, n^2 - l, or n^2 - 2 when l = 1.  Host-only; errors:
+ * PLSE_E_ARG (null). */
 int plse_info(plse_handle h, int32_t *num_vertices, int32_t *num_impossible,
               int32_t *upper_bound);
 
@@ -117,6 +121,11 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *                 table in global memory (the default, also 0); 2: the kernel
  *                 with the whole search state in LDS (MPMA only, when it fits
  *                 the device's per-block LDS).  Both give the same results.
+ *   "persistent"  1 (default): in plse_solve_batch, the tabu searches of the
+ *                 instances sharing a launch shape run as one persistent
+ *                 launch whose waves take (instance, individual) items,
+ *                 instances in order of estimated work (longest first); 0 (on
+ *                 any instance of the group): a grid of blocks per instance
  *   "stage_timing" 1: single-instance sessions enqueue each stage of a
  *                 generation on its own between HIP events (no graphs; the
  *                 distances among P_t run before the search instead of
@@ -155,6 +164,14 @@ int plse_get_param(plse_handle h, const char *key, int64_t *value);
  */
 int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, void *stream,
                   float *out_ms);
+
+/* plse_autotune_shape -- as plse_autotune, over chunk size and waves per
+ * block together: 9 timed shapes (slots per lane 2, 4, 8 for 1, then 2, then
+ * 4 waves per block; out_ms may be NULL, else 9 floats, -1 where a shape does
+ * not fit); the fastest is stored as "slots_per_lane" and "waves_per_block".
+ * Same errors. */
+int plse_autotune_shape(plse_handle h, int32_t sample, int32_t depth, uint64_t seed,
+                        void *stream, float *out_ms);
 
 /* Bytes of device workspace a solve with this population needs. */
 int plse_workspace_bytes(plse_handle h, int32_t population, size_t *bytes);
@@ -265,6 +282,25 @@ int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t population,
                      int8_t *const *best_grids, int32_t *filled);
 
 /*
+ * Session form of plse_solve_batch, for callers that step a batch in parts:
+ *   plse_batch_begin  holds the handles (each idle, distinct, with its
+ *                     workspace) and builds every initial population;
+ *   plse_batch_step   enqueues `generations` more generations of all of them;
+ *   plse_batch_end    waits for the stream, writes best_grids[i] / filled[i]
+ *                     for hs[i] of plse_batch_begin, fills each handle's
+ *                     statistics, releases the handles and frees the batch
+ *                     (also on error).
+ * plse_solve_batch(hs, count, p, G, ...) is begin + step(G) + end; the
+ * results are the same however the generations are split.  Errors as
+ * plse_solve_batch; plse_batch_step: PLSE_E_ARG beyond max_generations.
+ */
+typedef struct plse_batch_t *plse_batch;
+int plse_batch_begin(const plse_handle *hs, int32_t count, int32_t population,
+                     const uint64_t *seeds, void *stream, plse_batch *out);
+int plse_batch_step(plse_batch b, int32_t generations, void *stream);
+int plse_batch_end(plse_batch b, void *stream, int8_t *const *best_grids, int32_t *filled);
+
+/*
  * plse_solve_noalloc -- plse_solve for callers that cannot allocate device
  * memory or create runtime objects (code that must not call hipMalloc: tight
  * serving loops, harnesses that forbid allocation).  Instead of the handle's
@@ -314,9 +350,12 @@ int plse_last_timing(plse_handle h, int32_t *steps, float *plits_ms, float *rest
 #define PLSE_NSTAGES 7
 int plse_last_stage_timing(plse_handle h, int32_t *steps, float *ms);
 
-/* Statistics of the last solve; per_gen_best_f (may be NULL) receives the
- * best f after each generation (generations_run entries) and per_gen_counters
- * (may be NULL) PLSE_NCOUNTERS u64 per generation. */
+/* Statistics of the last solve, the per-run quantities of Tables 3-4 and
+ * Section 4.3 (best f and the generation that found it, the stop reason, and
+ * the tabu work: iterations, moves and the other PLSE_NCOUNTERS counters of
+ * Section 3.3's search); per_gen_best_f (may be NULL) receives the best f
+ * after each generation (generations_run entries) and per_gen_counters (may
+ * be NULL) PLSE_NCOUNTERS u64 per generation. */
 int plse_last_stats(plse_handle h, plse_stats *out, int32_t *per_gen_best_f,
                     uint64_t *per_gen_counters);
 

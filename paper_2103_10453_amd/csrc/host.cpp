@@ -55,6 +55,7 @@ struct Layout {
     size_t args, ctl, stats, Sstar;
     size_t S_all, S_off, S_tmp, f_all, f_tmp, uid, uid_tmp, hist, hist_tmp, hc, hc_tmp, cnt;
     size_t tabu, planes, D, deg, adj, keys, rej, acc, pos, hkeys, hvals, partner, dpart;
+    size_t queue;  // work queue of a persistent batched search launch led by this instance
     size_t total;
     int pow2_sel, hsize;
 };
@@ -102,6 +103,7 @@ struct plse_instance {
     int spl = 0;  // candidate positions per lane and round in PLITS; 0: automatic
     int wpb = 0;  // waves per block in PLITS; 0: automatic
     int kernel = 0;  // PLITS kernel: 0 automatic, 1 global tabu table, 2 LDS-resident
+    int persistent = 1;  // batched searches: one persistent launch per group (0: a grid per instance)
     int fail_at = 0;  // serving test hook: end the request after this generation
     int max_gens = PLSE_MAX_GENERATIONS;  // generations a session may run (sizes its records)
     int sel_global = 0;  // test hook: sort selection keys in global memory when possible
@@ -328,6 +330,7 @@ Layout plan(const plse_instance *h, int p) {
     L.hvals = take(4 * (size_t)L.hsize);
     L.partner = take(4 * (size_t)p);
     L.dpart = take(4 * (size_t)p);
+    L.queue = take(64);
     L.total = o;
     return L;
 }
@@ -539,6 +542,10 @@ int launch_ctl(const std::vector<plse_instance *> &hs, bool reset, hipStream_t s
 struct PlitsGroup {
     int spl = 8, occ = 0, lds = 0, wpb = 1;
     bool partial = false, lean = false;
+    // several instances: one persistent launch (per kMaxLaunch instances)
+    // whose waves take (instance, individual) items longest first
+    bool persistent = false;
+    int blocks = 0;
     std::vector<plse_instance *> hs;
 };
 
@@ -593,9 +600,32 @@ struct Session {
 };
 
 int launch_group(const Session &S, const PlitsGroup &g, hipStream_t s) {
+    if (g.persistent) {
+        for (size_t b = 0; b < g.hs.size(); b += kMaxLaunch) {
+            ArgList L{};
+            const int count = (int)std::min<size_t>(kMaxLaunch, g.hs.size() - b);
+            for (int i = 0; i < count; ++i) L.p[i] = dev_arg(g.hs[b + i], &ArgBlock::plits);
+            plse_instance *lead = g.hs[b];
+            HIP_TRY(launch_plits_persistent(L, count, S.p, g.lds, g.spl, g.wpb, g.partial,
+                                            g.blocks, at<uint32_t>(lead, lead->L.queue), s));
+        }
+        return PLSE_OK;
+    }
     return launch_over(g.hs, &ArgBlock::plits, [&](const ArgList &L, int c) {
         return launch_plits(L, c, S.p, g.lds, g.spl, g.wpb, g.partial, g.lean, s);
     });
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            cus = c;
+        (void)hipGetLastError();
+    }
+    return cus > 0 ? cus : 256;
 }
 
 // One generation's tabu searches.  Several groups run concurrently: group 0
@@ -779,6 +809,13 @@ void shape_session(Session &S) {
         g.wpb = (same_wpb && g.hs[0]->wpb) ? g.hs[0]->wpb
                                             : auto_wpb(g.lds, {g.spl}, g.partial, g.lean);
         if (g.wpb * g.lds > max_lds_per_block()) g.wpb = 1;
+        bool all_persistent = true;
+        for (plse_instance *h : g.hs) all_persistent = all_persistent && h->persistent != 0;
+        g.persistent = g.hs.size() > 1 && !g.lean && all_persistent;
+        if (g.persistent) {
+            const int occ = plits_waves_per_cu(g.spl, g.wpb, g.lds, g.partial, false, true);
+            g.blocks = std::max(1, occ * device_cus() / g.wpb);
+        }
     }
 }
 
@@ -1209,6 +1246,9 @@ int plse_set_param(plse_handle h, const char *key, int64_t v) {
     } else if (k == "stage_timing") {
         if (v != 0 && v != 1) return PLSE_E_PARAM;
         h->stage_timing = (int)v;
+    } else if (k == "persistent") {
+        if (v != 0 && v != 1) return PLSE_E_PARAM;
+        h->persistent = (int)v;
     } else if (k == "select_global_sort") {
         if (v != 0 && v != 1) return PLSE_E_PARAM;
         h->sel_global = (int)v;
@@ -1249,6 +1289,7 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "select_global_sort") *v = h->sel_global;
     else if (k == "plits_kernel") *v = plits_lds(h).lean ? 2 : 1;
     else if (k == "stage_timing") *v = h->stage_timing;
+    else if (k == "persistent") *v = h->persistent;
     else return PLSE_E_PARAM;
     return PLSE_OK;
 }
@@ -1531,6 +1572,71 @@ int plse_measure_lds_bandwidth(void *stream, int32_t repeats, double *bytes_per_
     return PLSE_OK;
 }
 
+}  // extern "C"
+
+// An open batched session (plse_batch_begin .. plse_batch_end): the session
+// over the instances and the guards that keep each handle busy meanwhile.
+struct plse_batch_t {
+    Session S;
+    std::vector<plse_instance *> order;  // caller's order
+    std::vector<BusyGuard *> guards;
+    ~plse_batch_t() {
+        for (BusyGuard *g : guards) delete g;
+    }
+};
+
+extern "C" {
+
+int plse_batch_begin(const plse_handle *hs, int32_t count, int32_t p, const uint64_t *seeds,
+                     void *stream, plse_batch *out) {
+    if (!hs || count < 1 || !seeds || !out) return PLSE_E_ARG;
+    *out = nullptr;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i]) return PLSE_E_ARG;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return PLSE_E_ARG;
+    }
+    plse_batch_t *b = new plse_batch_t();
+    int rc = PLSE_OK;
+    for (int i = 0; i < count && !rc; ++i) {
+        b->guards.push_back(new BusyGuard(hs[i]));
+        if (!b->guards.back()->ok || hs[i]->in_session) rc = PLSE_E_BUSY;
+    }
+    if (!rc) {
+        b->S.hs.assign(hs, hs + count);
+        b->S.p = p;
+        b->order.assign(hs, hs + count);
+        std::vector<uint64_t> sd(seeds, seeds + count);
+        rc = session_begin(b->S, sd.data(), reinterpret_cast<hipStream_t>(stream));
+    }
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return PLSE_OK;
+}
+
+int plse_batch_step(plse_batch b, int32_t generations, void *stream) {
+    if (!b || generations < 0) return PLSE_E_ARG;
+    return session_step(b->S, generations, reinterpret_cast<hipStream_t>(stream));
+}
+
+int plse_batch_end(plse_batch b, void *stream, int8_t *const *best_grids, int32_t *filled) {
+    if (!b) return PLSE_E_ARG;
+    int rc = PLSE_E_ARG;
+    if (best_grids && filled) {
+        bool ok = true;
+        for (size_t i = 0; i < b->order.size(); ++i) ok = ok && best_grids[i];
+        if (ok)
+            rc = session_end(b->S, reinterpret_cast<hipStream_t>(stream), b->order, best_grids,
+                             filled);
+    }
+    if (rc) (void)hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    delete b;
+    return rc;
+}
+
 int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t p, int32_t G,
                      const uint64_t *seeds, void *stream, int8_t *const *best_grids,
                      int32_t *filled) {
@@ -1649,12 +1755,15 @@ int plse_stage_plits(plse_handle h, int32_t p, int32_t gen, uint64_t seed, void 
     return PLSE_OK;
 }
 
-int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, void *stream,
-                  float *out_ms) {
-    if (!h || sample < 2 || depth < 1) return PLSE_E_ARG;
-    BusyGuard guard(h);
-    if (!guard.ok) return PLSE_E_BUSY;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace {
+
+// Times phase-1 searches of the initial population's first `sample`
+// individuals under each launch shape (chunk sizes 2, 4, 8; with `waves`
+// also 1, 2, 4 waves per block) and keeps the fastest on the handle.
+int autotune(plse_instance *h, int32_t sample, int32_t depth, uint64_t seed, hipStream_t s,
+             bool waves, float *out_ms) {
     RC_TRY(stage_prepare(h, sample, s));
     // the workspace's offspring, scratch and counter regions hold the sample
     uint8_t *S_in = at<uint8_t>(h, h->L.S_off), *S_out = at<uint8_t>(h, h->L.S_tmp);
@@ -1665,16 +1774,17 @@ int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, v
     RC_TRY(upload_args(h, s));
     HIP_TRY(launch_init(single(h, &ArgBlock::init), 1, sample,
                         init_lds_bytes(h->args.init.I, h->args.init.pow2), s));
-    // phase-1 searches of `depth` iterations per chunk size; the waves per
-    // block stay with the handle's setting (or the occupancy rule), which
-    // also weighs the uneven search lengths of later generations
+    // phase-1 searches of `depth` iterations per shape; without `waves` the
+    // waves per block stay with the handle's setting (or the occupancy
+    // rule, which also weighs the uneven search lengths of later generations)
     const Params saved = h->P;
-    const int spl0 = h->spl;
+    const int spl0 = h->spl, wpb0 = h->wpb;
     h->P.depth1 = depth;
     h->P.depth2 = 0;
-    const int spls[3] = {2, 4, 8};
-    float ms[3] = {};
-    bool fits[3] = {};
+    const int spls[3] = {2, 4, 8}, wpbs[3] = {1, 2, 4};
+    const int nshape = waves ? 9 : 3;
+    float ms[9] = {};
+    bool fits[9] = {};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = PLSE_OK;
     auto chk = [&](hipError_t e, const char *what) {
@@ -1682,10 +1792,11 @@ int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, v
     };
     chk(hipEventCreate(&e0), "hipEventCreate");
     chk(hipEventCreate(&e1), "hipEventCreate");
-    // pass 0: one untimed launch (code loading, caches); pass 1: every size
+    // pass 0: one untimed launch (code loading, caches); pass 1: every shape
     for (int pass = 0; pass < 2 && !rc; ++pass) {
-        for (int i = 0; i < 3 && !rc; ++i) {
-            h->spl = spls[i];
+        for (int i = 0; i < nshape && !rc; ++i) {
+            h->spl = spls[i % 3];
+            if (waves) h->wpb = wpbs[i / 3];
             const PlitsLds pl = plits_lds(h);
             const int per = pl.per_wave, wpb = choose_wpb(h);
             fits[i] = plits_fn(h->spl, h->P.variant != 0) != nullptr &&
@@ -1712,15 +1823,37 @@ int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, v
     if (e1) (void)hipEventDestroy(e1);
     h->P = saved;
     h->spl = spl0;
+    h->wpb = wpb0;
     if (rc) return rc;
     int best = -1;
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < nshape; ++i) {
         if (out_ms) out_ms[i] = fits[i] ? ms[i] : -1.0f;
         if (fits[i] && (best < 0 || ms[i] < ms[best])) best = i;
     }
     if (best < 0) return PLSE_E_ARG;
-    h->spl = spls[best];
+    h->spl = spls[best % 3];
+    if (waves) h->wpb = wpbs[best / 3];
     return PLSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plse_autotune(plse_handle h, int32_t sample, int32_t depth, uint64_t seed, void *stream,
+                  float *out_ms) {
+    if (!h || sample < 2 || depth < 1) return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok) return PLSE_E_BUSY;
+    return autotune(h, sample, depth, seed, reinterpret_cast<hipStream_t>(stream), false, out_ms);
+}
+
+int plse_autotune_shape(plse_handle h, int32_t sample, int32_t depth, uint64_t seed,
+                        void *stream, float *out_ms) {
+    if (!h || sample < 2 || depth < 1) return PLSE_E_ARG;
+    BusyGuard guard(h);
+    if (!guard.ok) return PLSE_E_BUSY;
+    return autotune(h, sample, depth, seed, reinterpret_cast<hipStream_t>(stream), true, out_ms);
 }
 
 int plse_stage_distances(plse_handle h, int32_t m, void *stream, const uint8_t *S, int16_t *D) {

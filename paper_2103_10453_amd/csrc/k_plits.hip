@@ -655,23 +655,10 @@ __device__ void repair(const PlitsArgs &a, const uint8_t *from, uint8_t *out, co
     PLSE_WAVE_SYNC();
 }
 
-}  // namespace
-
+// The search of individual `ind` of one instance in generation `gen`, by one
+// wave whose LDS starts at `base`.
 template <int CH, bool PARTIAL>
-__global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    // by reference: fields needed only before or after a phase are read when
-    // needed instead of being held in registers through the search
-    const PlitsArgs &a = *static_cast<const PlitsArgs *>(L.p[blockIdx.y]);
-    const int wv = (int)(threadIdx.x >> 6);
-    const int ind = (int)blockIdx.x * (int)(blockDim.x >> 6) + wv;
-    if (ind >= a.p) return;
-    int gen = a.gen_fixed;
-    if (gen == 0) {
-        if (gptr(a.ctl)->stop) return;
-        gen = gptr(a.ctl)->gen;
-    }
-    uint8_t *base = lds + (size_t)wv * a.lds_per_wave;
+__device__ void plits_individual(const PlitsArgs &a, int ind, int gen, uint8_t *base) {
     WaveState ws;
     ws.S = base;
     ws.H = base + a.off_h;
@@ -746,6 +733,58 @@ __global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
     if (lane == 0) gptr(a.f_out)[ind] = f_final;
 }
 
+}  // namespace
+
+template <int CH, bool PARTIAL>
+__global__ __launch_bounds__(256, 4) void plits_kernel(const ArgList L) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    // by reference: fields needed only before or after a phase are read when
+    // needed instead of being held in registers through the search
+    const PlitsArgs &a = *static_cast<const PlitsArgs *>(L.p[blockIdx.y]);
+    const int wv = (int)(threadIdx.x >> 6);
+    const int ind = (int)blockIdx.x * (int)(blockDim.x >> 6) + wv;
+    if (ind >= a.p) return;
+    int gen = a.gen_fixed;
+    if (gen == 0) {
+        if (gptr(a.ctl)->stop) return;
+        gen = gptr(a.ctl)->gen;
+    }
+    plits_individual<CH, PARTIAL>(a, ind, gen, lds + (size_t)wv * a.lds_per_wave);
+}
+
+// Persistent form for many instances: every wave takes (instance,
+// individual) items from a queue until it runs dry.  Items run instance by
+// instance in the order of the argument list (longest estimated work first),
+// individuals in order within an instance; stopped instances are skipped.
+// Every wave of the launch uses `lds_per_wave` bytes (the largest instance's).
+template <int CH, bool PARTIAL>
+__global__ __launch_bounds__(256, 4) void plits_persistent_kernel(const ArgList L, int count, int p,
+                                                                  int lds_per_wave,
+                                                                  uint32_t *queue) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint8_t *base = lds + (size_t)(threadIdx.x >> 6) * lds_per_wave;
+    const uint32_t total = (uint32_t)count * (uint32_t)p;
+    for (;;) {
+        uint32_t item = 0u;
+        if (lane_id() == 0) item = atomicAdd(queue, 1u);
+        item = readlane_u32(item, 0);
+        if (item >= total) break;
+        const uint32_t inst = item / (uint32_t)p, ind = item - inst * (uint32_t)p;
+        const PlitsArgs &a = *static_cast<const PlitsArgs *>(L.p[inst]);
+        int gen = a.gen_fixed;
+        if (gen == 0) {
+            if (gptr(a.ctl)->stop) continue;
+            gen = gptr(a.ctl)->gen;
+        }
+        plits_individual<CH, PARTIAL>(a, (int)ind, gen, base);
+        PLSE_WAVE_SYNC();
+    }
+}
+
+__global__ void queue_reset_kernel(uint32_t *queue) {
+    if (threadIdx.x == 0) *gptr(queue) = 0u;
+}
+
 // The PLITS kernel of a chunk size, MPMA or Partial-MPMA; null for other sizes.
 const void *plits_fn(int slots_per_lane, bool partial) {
     switch (slots_per_lane) {
@@ -778,6 +817,32 @@ hipError_t launch_plits(const ArgList &L, int count, int p, int lds_per_wave,
     return hipLaunchKernel(fn, grid, block, args, lds, stream);
 }
 
+const void *plits_persistent_fn(int slots_per_lane, bool partial) {
+    switch (slots_per_lane) {
+        case 2: return partial ? (const void *)plits_persistent_kernel<2, true>
+                               : (const void *)plits_persistent_kernel<2, false>;
+        case 4: return partial ? (const void *)plits_persistent_kernel<4, true>
+                               : (const void *)plits_persistent_kernel<4, false>;
+        case 8: return partial ? (const void *)plits_persistent_kernel<8, true>
+                               : (const void *)plits_persistent_kernel<8, false>;
+        default: return nullptr;
+    }
+}
+
+hipError_t launch_plits_persistent(const ArgList &L, int count, int p, int lds_per_wave,
+                                   int slots_per_lane, int waves_per_block, bool partial,
+                                   int blocks, uint32_t *queue, hipStream_t stream) {
+    const void *fn = plits_persistent_fn(slots_per_lane, partial);
+    if (!fn || blocks < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, stream, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)lds_per_wave * waves_per_block;
+    ArgList Lc = L;
+    void *args[] = {&Lc, &count, &p, &lds_per_wave, &queue};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(64 * waves_per_block), args, lds, stream);
+}
+
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
     hipLaunchKernelGGL(fill_zero_kernel, dim3(1024, count), dim3(256), 0, stream, L);
     return hipGetLastError();
@@ -786,8 +851,10 @@ hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream) {
 // Resident waves per CU of a PLITS launch shape (the runtime's occupancy
 // calculation: registers, LDS and workgroup limits).
 int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial,
-                       bool lean) {
-    const void *fn = lean ? plits_lean_fn(slots_per_lane) : plits_fn(slots_per_lane, partial);
+                       bool lean, bool persistent) {
+    const void *fn = lean ? plits_lean_fn(slots_per_lane)
+                          : (persistent ? plits_persistent_fn(slots_per_lane, partial)
+                                        : plits_fn(slots_per_lane, partial));
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64 * waves_per_block,
                                                      (size_t)lds_per_wave * waves_per_block) !=
@@ -804,6 +871,8 @@ hipError_t plits_set_lds_limit(int bytes) {
         for (bool partial : {false, true})
             if (e == hipSuccess) e = set_dynamic_lds_limit(plits_fn(spl, partial), bytes);
         if (e == hipSuccess) e = set_dynamic_lds_limit(plits_lean_fn(spl), bytes);
+        for (bool partial : {false, true})
+            if (e == hipSuccess) e = set_dynamic_lds_limit(plits_persistent_fn(spl, partial), bytes);
     }
     return e;
 }

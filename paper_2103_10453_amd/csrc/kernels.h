@@ -191,7 +191,13 @@ const void *plits_lean_fn(int slots_per_lane);
 hipError_t launch_fill_zero(const ArgList &L, int count, hipStream_t stream);
 hipError_t plits_set_lds_limit(int bytes);
 int plits_waves_per_cu(int slots_per_lane, int waves_per_block, int lds_per_wave, bool partial,
-                       bool lean);
+                       bool lean, bool persistent = false);
+// Persistent PLITS over `count` instances of population p: `blocks` blocks
+// take (instance, individual) items from *queue (zeroed first, by a kernel)
+// until all count * p are done.
+hipError_t launch_plits_persistent(const ArgList &L, int count, int p, int lds_per_wave,
+                                   int slots_per_lane, int waves_per_block, bool partial,
+                                   int blocks, uint32_t *queue, hipStream_t stream);
 hipError_t launch_init(const ArgList &L, int count, int p, size_t lds, hipStream_t stream);
 size_t init_lds_bytes(const DevInstance &I, int pow2);
 hipError_t init_set_lds_limit(int bytes);

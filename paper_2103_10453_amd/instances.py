@@ -174,8 +174,10 @@ def workload_batch(count: int = 256, base: int = 3000):
 def workload_served(count: int, rate: float, base: int = 4000):
     """Poisson request stream: exponential gaps at `rate` req/s, n ~ U{10..100},
     r ~ U[0.3, 0.7], planted or random-greedy by coin flip; population 2048,
-    50 generations.  Returns a list of dicts with an `arrival` time in seconds."""
-    meta = SplitMix64(base + int(rate * 1000))
+    50 generations.  Returns a list of dicts with an `arrival` time in seconds.
+    The requests and the order of their gaps do not depend on the rate: a
+    stream at another rate is the same stream with its gaps rescaled."""
+    meta = SplitMix64(base)
     t = 0.0
     out = []
     for k in range(count):

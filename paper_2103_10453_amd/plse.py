@@ -76,12 +76,16 @@ def _lib():
             "plse_solve": [P, i32, i32, u64, P, P, P],
             "plse_begin": [P, i32, u64, P],
             "plse_solve_batch": [P, i32, i32, i32, P, P, P, P],
+            "plse_batch_begin": [P, i32, i32, P, P, P],
+            "plse_batch_step": [P, i32, P],
+            "plse_batch_end": [P, P, P, P],
             "plse_solve_noalloc": [P, i32, i32, u64, P, P, P, P],
             "plse_measure_lds_bandwidth": [P, i32, P],
             "plse_step": [P, i32, P],
             "plse_end": [P, P, P, P],
             "plse_peek": [P, P, P],
             "plse_autotune": [P, i32, i32, u64, P, P],
+            "plse_autotune_shape": [P, i32, i32, u64, P, P],
             "plse_checkpoint": [P, P, P, sz, P],
             "plse_resume": [P, i32, P, P, sz],
             "plse_last_timing": [P, P, P, P],
@@ -121,9 +125,9 @@ def exported_symbols():
     L = _lib()
     names = ["plse_create", "plse_info", "plse_sizes", "plse_row_stride", "plse_set_param", "plse_get_param",
              "plse_workspace_bytes", "plse_attach_workspace", "plse_solve", "plse_solve_batch",
-             "plse_solve_noalloc", "plse_measure_lds_bandwidth",
+             "plse_solve_noalloc", "plse_batch_begin", "plse_batch_step", "plse_batch_end", "plse_measure_lds_bandwidth",
              "plse_begin",
-             "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_checkpoint", "plse_resume", "plse_last_timing", "plse_last_stage_timing", "plse_last_stats",
+             "plse_step", "plse_end", "plse_peek", "plse_autotune", "plse_autotune_shape", "plse_checkpoint", "plse_resume", "plse_last_timing", "plse_last_stage_timing", "plse_last_stats",
              "plse_destroy", "plse_strerror", "plse_stage_init", "plse_stage_plits",
              "plse_stage_distances", "plse_stage_select", "plse_stage_match", "plse_stage_aux",
              "plse_server_create", "plse_server_submit", "plse_server_poll", "plse_server_status",
@@ -253,6 +257,29 @@ def plse_solve_batch(handles, ns, population: int, generations: int, seeds, stre
     return [(grids[i], int(filled[i])) for i in range(count)]
 
 
+def plse_batch_begin(handles, population: int, seeds, stream=None):
+    count = len(handles)
+    hs = (ctypes.c_void_p * count)(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                     for h in handles])
+    sd = (ctypes.c_uint64 * count)(*[s & ((1 << 64) - 1) for s in seeds])
+    b = ctypes.c_void_p()
+    _check(_lib().plse_batch_begin(hs, count, population, sd, _stream(stream), ctypes.byref(b)),
+           "plse_batch_begin")
+    return b
+
+
+def plse_batch_step(b, generations: int, stream=None):
+    _check(_lib().plse_batch_step(b, generations, _stream(stream)), "plse_batch_step")
+
+
+def plse_batch_end(b, ns, stream=None):
+    grids = [np.zeros((n, n), dtype=np.int8) for n in ns]
+    gp = (ctypes.c_void_p * len(ns))(*[g.ctypes.data for g in grids])
+    filled = np.zeros(len(ns), dtype=np.int32)
+    _check(_lib().plse_batch_end(b, _stream(stream), gp, _np(filled)), "plse_batch_end")
+    return [(grids[i], int(filled[i])) for i in range(len(ns))]
+
+
 def plse_begin(h, population: int, seed: int, stream=None):
     _check(_lib().plse_begin(h, population, seed & ((1 << 64) - 1), _stream(stream)), "plse_begin")
 
@@ -281,6 +308,13 @@ def plse_autotune(h, sample: int, depth: int, seed: int, stream=None):
     _check(_lib().plse_autotune(h, sample, depth, seed & ((1 << 64) - 1), _stream(stream),
                                 _np(ms)), "plse_autotune")
     return ms
+
+
+def plse_autotune_shape(h, sample: int, depth: int, seed: int, stream=None):
+    ms = np.zeros(9, dtype=np.float32)
+    _check(_lib().plse_autotune_shape(h, sample, depth, seed & ((1 << 64) - 1), _stream(stream),
+                                      _np(ms)), "plse_autotune_shape")
+    return ms.reshape(3, 3)
 
 
 def plse_checkpoint(h, stream=None) -> np.ndarray:
@@ -446,6 +480,12 @@ class Solver:
         not fit)."""
         self.ensure_workspace(sample)
         return plse_autotune(self.h, sample, depth, seed, stream)
+
+    def autotune_shape(self, sample: int = 4096, depth: int = 2000, seed: int = 1, stream=None):
+        """Measure chunk size x waves per block and keep the fastest; returns
+        the times (ms) as [waves 1, 2, 4][slots 2, 4, 8] (-1: does not fit)."""
+        self.ensure_workspace(sample)
+        return plse_autotune_shape(self.h, sample, depth, seed, stream)
 
     def timing(self):
         return plse_last_timing(self.h)

@@ -60,3 +60,20 @@ def test_algorithmic_bytes_follow_the_move_definition():
     # colour (1) and tabu entry (2) per move; |V| per snapshot
     want = 100 * 4 + 36 * 4 + 10 * 8 + 9 * 3 + 2 * 60
     assert bench.plits_alg_bytes(cnt, nv) == want
+
+
+def test_fifo_replay_of_solo_service_times():
+    # arrivals 0, 1, 1.5, 10; service 2, 2, 1, 1: the second waits for the
+    # first, the third for the second, the fourth finds the server idle
+    start, finish = bench.fifo_latencies([0.0, 1.0, 1.5, 10.0], [2.0, 2.0, 1.0, 1.0])
+    assert start == [0.0, 2.0, 4.0, 10.0]
+    assert finish == [2.0, 4.0, 5.0, 11.0]
+
+
+def test_served_stream_rescales_with_the_rate():
+    from paper_2103_10453_amd import instances as gen
+    a = gen.workload_served(5, 10.0)
+    b = gen.workload_served(5, 40.0)
+    for x, y in zip(a, b):
+        assert (x["grid"] == y["grid"]).all() and x["seed"] == y["seed"]
+        assert x["arrival"] == pytest.approx(4.0 * y["arrival"])

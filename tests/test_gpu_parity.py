@@ -446,15 +446,20 @@ def test_full_size_n50_generation_sampled(torch_cuda, oracle_mod):
 
 
 # --- batched solve ---------------------------------------------------------------------
-def test_batch_equals_standalone_and_oracle(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_batch_equals_standalone_and_oracle(torch_cuda, oracle_mod, persistent):
     """plse_solve_batch over instances of different orders returns, for each,
-    exactly what plse_solve returns alone and what the oracle computes."""
-    names = ["greedy20_50", "planted10", "greedy12_60", "planted33_45"]
+    exactly what plse_solve returns alone and what the oracle computes, with
+    the searches as persistent launches over (instance, individual) items and
+    as a grid per instance."""
+    names = ["greedy20_50", "planted10", "greedy12_60", "planted33_45", "greedy70_70",
+             "planted10"]
     grids = [_instances()[k] for k in names]
-    _say("batch of 4 mixed instances p=32 G=4")
+    _say(f"batch of 6 mixed instances p=32 G=4 persistent={persistent}")
     p, G = 32, 4
     seeds = [11 + 7 * i for i in range(len(grids))]
-    solvers = [P.Solver(g, depth=int(10 * g.shape[0] ** 2 // 4)) for g in grids]
+    solvers = [P.Solver(g, depth=int(10 * g.shape[0] ** 2 // 4), persistent=persistent)
+               for g in grids]
     res = P.Solver.solve_batch(solvers, p, G, seeds)
     batch_stats = [s.stats() for s in solvers]
     for i, g in enumerate(grids):
@@ -469,6 +474,26 @@ def test_batch_equals_standalone_and_oracle(torch_cuda, oracle_mod):
         assert r["filled"] == res[i][1]
         np.testing.assert_array_equal(r["grid"], res[i][0])
         np.testing.assert_array_equal(r["counters"], batch_stats[i]["counters_per_gen"])
+
+
+def test_batch_session_steps_in_parts(torch_cuda):
+    """plse_batch_begin / step / step / end equals plse_solve_batch in one go."""
+    names = ["greedy20_50", "planted10", "planted33_45"]
+    grids = [_instances()[k] for k in names]
+    _say("batch session in parts")
+    p, seeds = 24, [5, 6, 7]
+    solvers = [P.Solver(g, depth=800) for g in grids]
+    ref = P.Solver.solve_batch(solvers, p, 3, seeds)
+    ref_cnt = [s.stats()["counters_per_gen"].copy() for s in solvers]
+    b = P.plse_batch_begin([s.h for s in solvers], p, seeds)
+    P.plse_batch_step(b, 2)
+    P.plse_batch_step(b, 1)
+    got = P.plse_batch_end(b, [g.shape[0] for g in grids])
+    for (g1, f1), (g2, f2), s, c in zip(ref, got, solvers, ref_cnt):
+        assert f1 == f2 and np.array_equal(g1, g2)
+        np.testing.assert_array_equal(s.stats()["counters_per_gen"], c)
+    # the handles are free again
+    solvers[0].solve(p, 1, 1)
 
 
 def test_batch_more_than_one_launch_chunk(torch_cuda, oracle_mod):
@@ -623,6 +648,33 @@ def test_autotune_keeps_the_fastest_fitting_shape_and_the_results(torch_cuda, or
         grid2, filled2 = s.solve(24, 3, sd)
         assert filled2 == r["filled"]
         np.testing.assert_array_equal(grid2, r["grid"])
+
+
+def test_autotune_shape_keeps_the_fastest_shape_and_the_results(torch_cuda, oracle_mod):
+    """plse_autotune_shape times chunk size x waves per block, keeps the
+    fastest pair, and a batch of instances tuned apart (different shapes in
+    one persistent launch group) still equals the oracle."""
+    names = ["greedy20_50", "planted33_45", "greedy12_60"]
+    grids = [_instances()[k] for k in names]
+    solvers = []
+    for k, g in zip(names, grids):
+        _say(f"autotune shape {k}")
+        s = P.Solver(g, depth=600)
+        ms = s.autotune_shape(sample=48, depth=300, seed=5)
+        assert ms.shape == (3, 3)
+        fit = ms >= 0
+        assert fit.any() and np.all(ms[fit] > 0)
+        w, c = np.unravel_index(int(np.argmin(np.where(fit, ms, np.inf))), ms.shape)
+        assert s.get_param("waves_per_block") == (1, 2, 4)[w]
+        assert s.get_param("slots_per_lane") == (2, 4, 8)[c]
+        solvers.append(s)
+    seeds = [81, 82, 83]
+    res = P.Solver.solve_batch(solvers, 24, 3, seeds)
+    for g, sd, (grid, filled) in zip(grids, seeds, res):
+        I = oracle_mod.Instance(g)
+        r = I.run(I.params(depth=600), 24, 3, sd)
+        assert filled == r["filled"]
+        np.testing.assert_array_equal(grid, r["grid"])
 
 
 def test_c_example_solves_like_the_oracle(torch_cuda, oracle_mod):
