@@ -368,7 +368,8 @@ def main():
                    "depth": int(w["depth"]),
                    "slots_per_lane": int(s.get_param("slots_per_lane")),
                    "vertices": s.nv, "sum_domain": s.nd,
-                   "waves_per_block": int(s.get_param("waves_per_block"))},
+                   "waves_per_block": int(s.get_param("waves_per_block")),
+                   "resident_waves_per_cu": int(s.get_param("plits_waves_per_cu"))},
         "roofline": {"bound": "lds", "achieved": achieved, "peak": lds_peak, "unit": "GB/s",
                      "frac": achieved / lds_peak, "traffic": traffic, "kernel": kernel,
                      "bytes_per_launch": b_launch,

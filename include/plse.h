@@ -126,6 +126,9 @@ int plse_row_stride(plse_handle h, int32_t *stride);
  *                 launch whose waves take (instance, individual) items,
  *                 instances in order of estimated work (longest first); 0 (on
  *                 any instance of the group): a grid of blocks per instance
+ *   "plits_waves_per_cu" (plse_get_param only): resident tabu-search waves
+ *                 per CU under the handle's launch shape (the runtime's
+ *                 occupancy calculation; needs the HIP runtime)
  *   "stage_timing" 1: single-instance sessions enqueue each stage of a
  *                 generation on its own between HIP events (no graphs; the
  *                 distances among P_t run before the search instead of
@@ -291,8 +294,9 @@ int plse_solve_batch(const plse_handle *hs, int32_t count, int32_t population,
  *                     statistics, releases the handles and frees the batch
  *                     (also on error).
  * plse_solve_batch(hs, count, p, G, ...) is begin + step(G) + end; the
- * results are the same however the generations are split.  Errors as
- * plse_solve_batch; plse_batch_step: PLSE_E_ARG beyond max_generations.
+ * results are the same however the generations are split.  One call at a
+ * time per batch.  Errors as plse_solve_batch; plse_batch_step: PLSE_E_ARG
+ * beyond max_generations.
  */
 typedef struct plse_batch_t *plse_batch;
 int plse_batch_begin(const plse_handle *hs, int32_t count, int32_t population,

@@ -871,6 +871,12 @@ int session_step(Session &S, int generations, hipStream_t s) {
             HIP_TRY(hipEventRecord(m[2], s));
             RC_TRY(enqueue_rest(S, s, &m[3]));
             HIP_TRY(hipEventRecord(m[7], s));
+            if (S.stop_host) {
+                plse_instance *h = S.hs[0];
+                HIP_TRY(hipMemcpyAsync(S.stop_host + (S.steps + g) % Session::kStopRing,
+                                       &at<Ctl>(h, h->L.ctl)->stop, sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, s));
+            }
             HIP_TRY(hipEventRecord(S.ev[k + 2], s));
         }
         S.steps += generations;
@@ -1289,6 +1295,13 @@ int plse_get_param(plse_handle h, const char *key, int64_t *v) {
     else if (k == "select_global_sort") *v = h->sel_global;
     else if (k == "plits_kernel") *v = plits_lds(h).lean ? 2 : 1;
     else if (k == "stage_timing") *v = h->stage_timing;
+    else if (k == "plits_waves_per_cu") {
+        // resident tabu-search waves per CU of this handle's launch shape
+        // (registers, LDS and workgroup limits of the runtime's calculation)
+        set_attributes_once();
+        const PlitsLds pl = plits_lds(h);
+        *v = plits_waves_per_cu(choose_spl(h), choose_wpb(h), pl.per_wave, P.variant != 0, pl.lean);
+    }
     else if (k == "persistent") *v = h->persistent;
     else return PLSE_E_PARAM;
     return PLSE_OK;
