@@ -233,15 +233,16 @@ def main():
                     help="batch with one half: save its grids here, or compare with the "
                          "other half's saved grids if the file exists; served: where the "
                          "solo part saves its results and the served part reads them")
-    ap.add_argument("--requests", type=int, default=16, help="served: number of requests")
+    ap.add_argument("--requests", type=int, default=64, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served: arrivals per second")
     ap.add_argument("--rates", default="",
                     help="served: comma-separated arrival rates (one JSON line each)")
     ap.add_argument("--served-part", default="both", choices=["both", "solo", "served"],
                     help="served: run the solo baseline, the served streams, or both "
                          "(see --results-file)")
-    ap.add_argument("--max-slots", type=int, default=64,
-                    help="served: requests resident at once (admission limit)")
+    ap.add_argument("--max-slots", type=int, default=0,
+                    help="served: requests resident at once (admission limit; 0: one per "
+                         "hardware queue, since requests sharing a queue wait for each other)")
     ap.add_argument("--generations", type=int, default=0,
                     help="served: generations per request (default 50)")
     ap.add_argument("--hw-queues", type=int, default=16,
@@ -620,9 +621,10 @@ def bench_served(args, gen, plse):
         return
     free = torch.cuda.mem_get_info()[0]
     budget = int(0.7 * free) // 256 * 256
+    max_slots = args.max_slots or int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
     for rate in rates:
         reqs = [dict(r, arrival=r["arrival"] / rate) for r in unit]
-        srv = plse.Server(budget, max_slots=args.max_slots)
+        srv = plse.Server(budget, max_slots=max_slots)
         tickets, results = [], {}
         t0 = time.perf_counter()
         i = 0
@@ -656,7 +658,7 @@ def bench_served(args, gen, plse):
                                    "random-greedy, population 2048, depth 10n^2",
                        "requests": len(reqs), "rate": rate, "generations": G,
                        "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
-                       "max_slots": args.max_slots, "arena_bytes": budget},
+                       "max_slots": max_slots, "arena_bytes": budget},
             "wall_s": wall, "moves_per_s": moves / wall,
             "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
             "time_to_best_s": {"p50": pct(ttb, 50), "p99": pct(ttb, 99)}}
