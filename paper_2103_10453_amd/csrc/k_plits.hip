@@ -658,7 +658,7 @@ __device__ void repair(const PlitsArgs &a, const uint8_t *from, uint8_t *out, co
 // The search of individual `ind` of one instance in generation `gen`, by one
 // wave whose LDS starts at `base`.
 template <int CH, bool PARTIAL>
-__device__ void plits_individual(const PlitsArgs &a, int ind, int gen, uint8_t *base) {
+__device__ __forceinline__ void plits_individual(const PlitsArgs &a, int ind, int gen, uint8_t *base) {
     WaveState ws;
     ws.S = base;
     ws.H = base + a.off_h;
