@@ -79,6 +79,9 @@ def test_plits_parity(torch_cuda, oracle_mod, name, p, depth, spl, wpb, kernel):
     _say(f"plits {name} p={p} depth={depth} spl={spl} wpb={wpb} kernel={kernel}")
     s = P.Solver(g, depth=depth, slots_per_lane=spl, waves_per_block=wpb, plits_kernel=kernel)
     assert s.get_param("plits_kernel") == kernel
+    # resident waves per CU of the chosen launch shape: at least one, at most
+    # the 32 wave slots of a CU
+    assert 1 <= s.get_param("plits_waves_per_cu") <= 32
     seed, gen_no = 777 + p, 3
     S0, _ = s.stage_init(p, seed)
     S1, f1, c1 = s.stage_plits(S0, gen_no, seed)
