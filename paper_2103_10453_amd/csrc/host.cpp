@@ -560,7 +560,7 @@ struct Session {
     int base = 0;   // generations run before it (a session resumed from a checkpoint)
     uint64_t seed = 0;  // single-instance sessions
     std::vector<PlitsGroup> groups;  // largest estimated work first
-    hipGraphExec_t ls = nullptr, rest = nullptr;  // ls only with a single group
+    hipGraphExec_t ls = nullptr, rest = nullptr;  // a generation's searches; the rest
     std::vector<hipEvent_t> ev;                   // 3 per generation
     bool staged = false;                          // stage timing: kStages + 1 events per generation
     std::vector<hipEvent_t> sev;
@@ -629,7 +629,8 @@ int device_cus() {
 }
 
 // One generation's tabu searches.  Several groups run concurrently: group 0
-// on `s`, the others on side streams forked from and joined back into `s`.
+// on `s`, the others on side streams forked from and joined back into `s`
+// (captured, they become the parallel branches of the generation's graph).
 int enqueue_local_search(Session &S, hipStream_t s) {
     RC_TRY(launch_ctl(S.hs, false, s));
     if (S.groups.size() == 1) return launch_group(S, S.groups[0], s);
@@ -823,15 +824,14 @@ void shape_session(Session &S) {
 int session_begin(Session &S, const uint64_t *seeds, hipStream_t s) {
     RC_TRY(admit(S.hs, S.p, seeds, s));
     shape_session(S);
-    // a single group's generation is one graph; several groups are enqueued
-    // on forked streams each generation, so they run side by side
+    // a generation's searches are one graph (several groups: forked branches
+    // that run side by side), the rest another
     S.staged = S.hs.size() == 1 && S.hs[0]->stage_timing != 0;
     if (S.staged) {
         S.steps = 0;
         return PLSE_OK;  // stages enqueued one by one, each bracketed by events
     }
-    if (S.groups.size() == 1)
-        RC_TRY(capture([&](hipStream_t cs) { return enqueue_local_search(S, cs); }, &S.ls));
+    RC_TRY(capture([&](hipStream_t cs) { return enqueue_local_search(S, cs); }, &S.ls));
     RC_TRY(capture([&](hipStream_t cs) { return enqueue_rest(S, cs); }, &S.rest));
     if (old_tiles(S.p) > 0) {
         RC_TRY(capture([&](hipStream_t cs) { return enqueue_old_dist(S, cs); }, &S.dold));
