@@ -479,6 +479,32 @@ def test_batch_equals_standalone_and_oracle(torch_cuda, oracle_mod, persistent):
         np.testing.assert_array_equal(r["counters"], batch_stats[i]["counters_per_gen"])
 
 
+def test_batch_mixed_searches_equal_standalone(torch_cuda, oracle_mod):
+    """A batch whose instances need different search launches (Partial-MPMA,
+    the LDS-resident kernel, MPMA at two chunk sizes) forms several launch
+    groups, captured as branches of one graph per generation; each instance
+    still returns exactly what it returns alone, and the oracle's result."""
+    specs = [("greedy20_50", dict(variant=1)), ("planted33_45", dict(variant=1)),
+             ("greedy12_60", dict(plits_kernel=2)), ("greedy20_50", dict(slots_per_lane=4)),
+             ("planted10", dict()), ("greedy70_70", dict())]
+    _say("batch of 6 instances with different search launches p=24 G=3")
+    p, G = 24, 3
+    seeds = [31 + 5 * i for i in range(len(specs))]
+    depth = lambda g: int(10 * g.shape[0] ** 2 // 4)
+    grids = [_instances()[k] for k, _ in specs]
+    solvers = [P.Solver(g, depth=depth(g), **kw) for g, (_, kw) in zip(grids, specs)]
+    res = P.Solver.solve_batch(solvers, p, G, seeds)
+    for i, (g, (name, kw)) in enumerate(zip(grids, specs)):
+        alone = P.Solver(g, depth=depth(g), **kw)
+        grid, filled = alone.solve(p, G, seeds[i])
+        assert filled == res[i][1], name
+        np.testing.assert_array_equal(grid, res[i][0])
+    I = oracle_mod.Instance(grids[0])
+    r = I.run(I.params(depth=depth(grids[0]), variant=oracle_mod.V_PARTIAL), p, G, seeds[0])
+    assert r["filled"] == res[0][1]
+    np.testing.assert_array_equal(r["grid"], res[0][0])
+
+
 def test_batch_session_steps_in_parts(torch_cuda):
     """plse_batch_begin / step / step / end equals plse_solve_batch in one go."""
     names = ["greedy20_50", "planted10", "planted33_45"]
