@@ -591,6 +591,30 @@ def test_served_results_equal_alone_and_in_mix(torch_cuda):
         srv.close()
 
 
+def test_served_variants_equal_alone(torch_cuda):
+    """Requests with Partial-MPMA, the LDS-resident search kernel, the UX
+    crossover and random matching, served together, each return what
+    plse_solve returns for them alone."""
+    _say("serving: variants in one mix")
+    specs = [(gen.random_greedy(20, 0.5, 7), dict(variant=1)),
+             (gen.planted(33, 0.45, 9), dict(plits_kernel=2)),
+             (gen.random_greedy(12, 0.6, 5), dict(crossover=1, matching=1)),
+             (gen.random_greedy(15, 0.4, 21), dict(slots_per_lane=2, waves_per_block=2))]
+    p, G = 16, 3
+    want = [P.Solver(g, depth=300, **kw).solve(p, G, 40 + i) for i, (g, kw) in enumerate(specs)]
+    srv = P.Server(1 << 30, max_slots=4)
+    try:
+        tickets = [srv.submit(P.Solver(g, depth=300, **kw), p, G, 40 + i)
+                   for i, (g, kw) in enumerate(specs)]
+        res = _wait(srv, tickets)
+        for i, t in enumerate(tickets):
+            assert res[t]["status"] == P.PLSE_OK
+            assert res[t]["filled"] == want[i][1]
+            np.testing.assert_array_equal(res[t]["grid"], want[i][0])
+    finally:
+        srv.close()
+
+
 def test_server_capacity_and_fault_isolation(torch_cuda):
     _say("serving: capacity refusal and fault hook")
     small = P.Solver(gen.planted(10, 0.4, 0), depth=200)
